@@ -1,0 +1,234 @@
+"""ctypes binding of the FP64 CPU oracle (frt_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the package smoke check and the
+benchmark's CPU-baseline leg use this module; the GPU library never does.
+It accepts the plain job dictionaries produced by ``workloads.py`` (float32
+values) and widens every parameter to double.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build_oracle
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+c_double3 = ctypes.c_double * 3
+c_double4 = ctypes.c_double * 4
+
+STATUS_MISS_BOUNDS = 0
+STATUS_MISS_TMAX = 1
+STATUS_HIT = 2
+STATUS_HIT_CUT = 3
+STATUS_HIT_EXHAUSTED = 4
+FLAG_SHADOWED = 8
+FLAG_UNREFINED = 16
+FLAG_JUMP = 32          # oracle only: the root bracket closed on a jump of the estimate
+
+# Jacobian column slots (see oracle_pixel_jacobian)
+SLOT_C = slice(0, 4)
+SLOT_POWER = 4
+SLOT_PLANE = (slice(5, 9), slice(9, 13))
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", c_double3), ("target", c_double3), ("up", c_double3),
+                ("fov_y_deg", ctypes.c_double), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class Fractal(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("c", c_double4), ("power", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("bailout2", ctypes.c_double),
+                ("bound_radius", ctypes.c_double)]
+
+
+class Plane(ctypes.Structure):
+    _fields_ = [("n", c_double3), ("d", ctypes.c_double)]
+
+
+class March(ctypes.Structure):
+    _fields_ = [("max_steps", ctypes.c_int32), ("eps_abs", ctypes.c_double), ("eps_rel", ctypes.c_double),
+                ("step_clamp", ctypes.c_double), ("t_max", ctypes.c_double),
+                ("normal_mode", ctypes.c_int32), ("shadow", ctypes.c_int32),
+                ("light", c_double3), ("albedo", c_double3),
+                ("k_ambient", ctypes.c_double), ("k_diffuse", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liboracle.so, building it first when it is absent."""
+    global _lib
+    if _lib is None:
+        path = build_oracle.LIB
+        if not os.path.exists(path):
+            build_oracle.build()
+        L = ctypes.CDLL(path)
+        P = ctypes.POINTER
+        dp = P(ctypes.c_double)
+        L.oracle_quat_square.argtypes = [dp, dp]
+        L.oracle_bulb_power.argtypes = [dp, ctypes.c_double, dp]
+        L.oracle_escape_iters.argtypes = [P(Fractal), dp, ctypes.c_int32]
+        L.oracle_escape_iters.restype = ctypes.c_int32
+        L.oracle_de.argtypes = [P(Fractal), dp, ctypes.c_int64, dp, P(ctypes.c_int32), dp, dp]
+        L.oracle_bound_radius.argtypes = [P(Fractal)]
+        L.oracle_bound_radius.restype = ctypes.c_double
+        L.oracle_camera_ray.argtypes = [P(Camera), ctypes.c_int32, ctypes.c_int32, dp, dp]
+        L.oracle_render.argtypes = [P(Camera), P(Fractal), P(Plane), ctypes.c_int32, P(March),
+                                    P(ctypes.c_int64), ctypes.c_int64, ctypes.c_int32,
+                                    dp, dp, dp, P(ctypes.c_uint8), P(ctypes.c_int32), P(ctypes.c_int32),
+                                    P(ctypes.c_int64), P(ctypes.c_int64), dp]
+        L.oracle_render.restype = ctypes.c_int
+        L.oracle_pixel_jacobian.argtypes = [P(Camera), P(Fractal), P(Plane), ctypes.c_int32, P(March),
+                                            P(ctypes.c_int64), ctypes.c_int64, ctypes.c_int32,
+                                            dp, P(ctypes.c_int32)]
+        L.oracle_pixel_jacobian.restype = ctypes.c_int
+        L.oracle_max_threads.restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def make_camera(cam):
+    return Camera(c_double3(*cam["eye"]), c_double3(*cam["target"]), c_double3(*cam["up"]),
+                  float(cam["fov_y_deg"]), int(cam["width"]), int(cam["height"]))
+
+
+def make_fractal(fr):
+    kind = {"julia": 0, "bulb": 1}[fr["kind"]]
+    c = list(fr.get("c", (0.0, 0.0, 0.0, 0.0)))
+    return Fractal(kind, c_double4(*c), float(fr.get("power", 8.0)), int(fr["max_iter"]), float(fr["bailout2"]),
+                   float(fr.get("bound_radius", 0.0)))
+
+
+def make_planes(planes):
+    arr = (Plane * 2)()
+    for k, pl in enumerate(planes):
+        arr[k] = Plane(c_double3(*pl["n"]), float(pl["d"]))
+    return arr, len(planes)
+
+
+def make_march(m):
+    mode = {"tetra": 0, "central": 1}[m["normal_mode"]]
+    return March(int(m["max_steps"]), float(m["eps_abs"]), float(m["eps_rel"]), float(m["step_clamp"]),
+                 float(m["t_max"]), mode, int(bool(m["shadow"])), c_double3(*m["light_dir"]),
+                 c_double3(*m["albedo"]), float(m["k_ambient"]), float(m["k_diffuse"]))
+
+
+def max_threads():
+    return int(lib().oracle_max_threads())
+
+
+def render(job, pixels=None, threads=0):
+    """Render a job (all pixels, or the listed linear indices j*W+i).
+
+    Returns a dict of numpy arrays: depth [n], normal [3,n], colour [3,n],
+    status [n] (uint8), steps [n], hit_iters [n], de_evals [n],
+    orbit_bodies [n], raw_t [n].
+    """
+    L = lib()
+    cam, fr, mc = make_camera(job["camera"]), make_fractal(job["fractal"]), make_march(job["march"])
+    pl, npl = make_planes(job.get("planes", []))
+    if pixels is None:
+        n = int(cam.width) * int(cam.height)
+        pix = None
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int64)
+        n = pix.size
+    out = {
+        "depth": np.empty(n), "normal": np.empty((3, n)), "colour": np.empty((3, n)),
+        "status": np.empty(n, np.uint8), "steps": np.empty(n, np.int32), "hit_iters": np.empty(n, np.int32),
+        "de_evals": np.empty(n, np.int64), "orbit_bodies": np.empty(n, np.int64), "raw_t": np.empty(n),
+    }
+    rc = L.oracle_render(ctypes.byref(cam), ctypes.byref(fr), pl, npl, ctypes.byref(mc),
+                         _ptr(pix, ctypes.c_int64), n, int(threads),
+                         _ptr(out["depth"], ctypes.c_double), _ptr(out["normal"], ctypes.c_double),
+                         _ptr(out["colour"], ctypes.c_double), _ptr(out["status"], ctypes.c_uint8),
+                         _ptr(out["steps"], ctypes.c_int32), _ptr(out["hit_iters"], ctypes.c_int32),
+                         _ptr(out["de_evals"], ctypes.c_int64), _ptr(out["orbit_bodies"], ctypes.c_int64),
+                         _ptr(out["raw_t"], ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError("oracle_render failed")
+    return out
+
+
+def pixel_jacobian(job, pixels, threads=0):
+    """Per-pixel Jacobian [n, 7, 13] (rows depth, normal xyz, colour rgb;
+    columns c0-c3, power, plane0 n xyz d, plane1 n xyz d) and the escape
+    counts at the hit point and every normal tap [n, 7]."""
+    L = lib()
+    cam, fr, mc = make_camera(job["camera"]), make_fractal(job["fractal"]), make_march(job["march"])
+    pl, npl = make_planes(job.get("planes", []))
+    pix = np.ascontiguousarray(pixels, dtype=np.int64)
+    n = pix.size
+    jac = np.zeros((n, 7, 13))
+    taps = np.zeros((n, 7), np.int32)
+    rc = L.oracle_pixel_jacobian(ctypes.byref(cam), ctypes.byref(fr), pl, npl, ctypes.byref(mc),
+                                 _ptr(pix, ctypes.c_int64), n, int(threads),
+                                 _ptr(jac, ctypes.c_double), _ptr(taps, ctypes.c_int32))
+    if rc != 0:
+        raise RuntimeError("oracle_pixel_jacobian failed")
+    return jac, taps
+
+
+def de(fractal, points):
+    """Distance estimate at points [n,3]: (d, escape count, final |z|^2,
+    running derivative: dz2 for Julia, dr for the Mandelbulb)."""
+    L = lib()
+    fr = make_fractal(fractal)
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    n = pts.shape[0]
+    d, it, m2, dv = np.empty(n), np.empty(n, np.int32), np.empty(n), np.empty(n)
+    L.oracle_de(ctypes.byref(fr), _ptr(pts, ctypes.c_double), n, _ptr(d, ctypes.c_double),
+                _ptr(it, ctypes.c_int32), _ptr(m2, ctypes.c_double), _ptr(dv, ctypes.c_double))
+    return d, it, m2, dv
+
+
+def escape_iters(fractal, points, max_iter):
+    fr = make_fractal(fractal)
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    out = np.empty(pts.shape[0], np.int32)
+    L = lib()
+    for i in range(pts.shape[0]):
+        out[i] = L.oracle_escape_iters(ctypes.byref(fr), _ptr(pts[i], ctypes.c_double), int(max_iter))
+    return out
+
+
+def bound_radius(fractal):
+    return float(lib().oracle_bound_radius(ctypes.byref(make_fractal(fractal))))
+
+
+def quat_square(z):
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    out = np.empty(4)
+    lib().oracle_quat_square(_ptr(z, ctypes.c_double), _ptr(out, ctypes.c_double))
+    return out
+
+
+def bulb_power(w, n):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    out = np.empty(3)
+    lib().oracle_bulb_power(_ptr(w, ctypes.c_double), float(n), _ptr(out, ctypes.c_double))
+    return out
+
+
+def camera_rays(camera, pixels):
+    """Origins and unit directions [n,3] for linear pixel indices."""
+    L = lib()
+    cam = make_camera(camera)
+    pix = np.asarray(pixels, dtype=np.int64).ravel()
+    o = np.empty((pix.size, 3))
+    d = np.empty((pix.size, 3))
+    for k, lin in enumerate(pix):
+        oo, dd = np.empty(3), np.empty(3)
+        L.oracle_camera_ray(ctypes.byref(cam), int(lin % cam.width), int(lin // cam.width),
+                            _ptr(oo, ctypes.c_double), _ptr(dd, ctypes.c_double))
+        o[k], d[k] = oo, dd
+    return o, d
