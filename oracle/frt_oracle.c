@@ -214,6 +214,131 @@ void oracle_de(const or_fractal* f, const double* pts, int64_t n_pts,
     }
 }
 
+/* Tetrahedron vertices of Eq. 5. */
+static const double TETRA[4][3] = { { 1, -1, -1 }, { -1, -1, 1 }, { -1, 1, -1 }, { 1, 1, 1 } };
+
+/* ------------------------------------------------------------------------ */
+/* Conditioning probe: the estimate with a relative perturbation of size     */
+/* `rel` (uniform in [-rel, rel], one draw per component per body) applied   */
+/* to the power z^p of every body before c is added -- a Monte-Carlo model   */
+/* of rounding in a lower precision, placed where it matters: near the set   */
+/* z^p + c cancels, so the absolute error of z^p becomes a large relative    */
+/* error of the sum that the next body multiplies again.  Draws come from    */
+/* SplitMix64 (Steele, Lea and Flood, 2014) keyed by (seed, point, body,     */
+/* component).                                                               */
+/* ------------------------------------------------------------------------ */
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+static double noise(uint64_t seed, uint64_t point, int body, int comp, double rel) {
+    uint64_t h = splitmix64(seed ^ splitmix64(point * 0x100000001B3ull + (uint64_t)body * 8u + (uint64_t)comp));
+    double u = (double)(h >> 11) * (1.0 / 9007199254740992.0);   /* [0, 1) */
+    return 1.0 + rel * (2.0 * u - 1.0);
+}
+
+static double perturbed_de(const or_fractal* f, const double p[3], double rel, uint64_t seed, uint64_t key) {
+    if (f->kind == 0) {
+        double z[4] = { p[0], p[1], p[2], 0.0 };
+        double dz2 = 1.0, m2 = 0.0;
+        for (int32_t i = 0; i < f->max_iter; ++i) {
+            dz2 *= 4.0 * (z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3]);
+            double sq[4];
+            oracle_quat_square(z, sq);
+            for (int k = 0; k < 4; ++k) z[k] = sq[k] * noise(seed, key, i, k, rel) + f->c[k];
+            m2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3];
+            if (m2 > f->bailout2) break;
+        }
+        return (m2 == 0.0) ? 0.0 : 0.25 * log(m2) * sqrt(m2 / dz2);
+    }
+    double w[3] = { p[0], p[1], p[2] };
+    double m = dot3(w, w), dr = 1.0;
+    for (int32_t i = 0; i < f->max_iter; ++i) {
+        double r = sqrt(m);
+        dr = f->power * pow(r, f->power - 1.0) * dr + 1.0;
+        double wn[3];
+        oracle_bulb_power(w, f->power, wn);
+        for (int k = 0; k < 3; ++k) w[k] = wn[k] * noise(seed, key, i, k, rel) + p[k];
+        m = dot3(w, w);
+        if (m > f->bailout2) break;
+    }
+    return (m == 0.0) ? 0.0 : 0.25 * log(m) * sqrt(m) / dr;
+}
+
+/* Normal (R10) at points with the perturbed estimate at every tap. */
+void oracle_normal_perturbed(const or_fractal* f, const double* pts, const double* dirs, const double* eps,
+                             int64_t n, int32_t mode, double rel, uint64_t seed, double* out) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        const double* p = pts + 3 * i;
+        double g[3] = { 0, 0, 0 };
+        if (mode == 0) {
+            double h = 0.5773 * eps[i];
+            for (int a = 0; a < 4; ++a) {
+                double q[3] = { p[0] + h * TETRA[a][0], p[1] + h * TETRA[a][1], p[2] + h * TETRA[a][2] };
+                double d = perturbed_de(f, q, rel, seed, (uint64_t)i * 8u + (uint64_t)a);
+                for (int k = 0; k < 3; ++k) g[k] += TETRA[a][k] * d;
+            }
+        } else {
+            for (int k = 0; k < 3; ++k) {
+                double qp[3] = { p[0], p[1], p[2] }, qm[3] = { p[0], p[1], p[2] };
+                qp[k] += eps[i];
+                qm[k] -= eps[i];
+                g[k] = perturbed_de(f, qp, rel, seed, (uint64_t)i * 8u + (uint64_t)(2 * k)) -
+                       perturbed_de(f, qm, rel, seed, (uint64_t)i * 8u + (uint64_t)(2 * k + 1));
+            }
+        }
+        double l = sqrt(dot3(g, g));
+        for (int k = 0; k < 3; ++k) out[3 * i + k] = l > 0.0 ? g[k] / l : -dirs[3 * i + k];
+    }
+}
+
+/* Escape-decision margin of the orbit at p: the smallest relative distance
+ * | |z_k|^2 - bailout2 | / bailout2 over the executed bodies, and whether the
+ * orbit escaped.  A small margin means the escape count (and so the estimate,
+ * which jumps where the count changes) is decided by rounding.             */
+static double escape_margin(const or_fractal* f, const double p[3], int* escaped) {
+    double best = INFINITY;
+    *escaped = 0;
+    if (f->kind == 0) {
+        double z[4] = { p[0], p[1], p[2], 0.0 };
+        for (int32_t i = 0; i < f->max_iter; ++i) {
+            double sq[4];
+            oracle_quat_square(z, sq);
+            for (int k = 0; k < 4; ++k) z[k] = sq[k] + f->c[k];
+            double m2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3];
+            best = fmin(best, fabs(m2 - f->bailout2) / f->bailout2);
+            if (m2 > f->bailout2) { *escaped = 1; break; }
+        }
+    } else {
+        double w[3] = { p[0], p[1], p[2] };
+        for (int32_t i = 0; i < f->max_iter; ++i) {
+            double wn[3];
+            oracle_bulb_power(w, f->power, wn);
+            w[0] = wn[0] + p[0]; w[1] = wn[1] + p[1]; w[2] = wn[2] + p[2];
+            double m = dot3(w, w);
+            best = fmin(best, fabs(m - f->bailout2) / f->bailout2);
+            if (m > f->bailout2) { *escaped = 1; break; }
+        }
+    }
+    return best;
+}
+
+void oracle_escape_margin(const or_fractal* f, const double* pts, int64_t n, double* margin, int32_t* escaped) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        int e;
+        margin[i] = escape_margin(f, pts + 3 * i, &e);
+        if (escaped) escaped[i] = e;
+    }
+}
+
 /* Bounding-sphere radius (R7): any point farther out escapes.
  * Julia: |z| > (1 + sqrt(1 + 4|c|))/2 implies |z^2 + c| >= |z|^2 - |c| > |z|.
  * Mandelbulb: |p^n| = r^n, so the Multibrot bound 2^(1/(n-1)) applies.     */
@@ -372,7 +497,6 @@ static double refine_root(const or_fractal* f, const double o[3], const double d
 }
 
 /* R10: normal at p from distance taps.  A zero gradient falls back to -dir. */
-static const double TETRA[4][3] = { { 1, -1, -1 }, { -1, -1, 1 }, { -1, 1, -1 }, { 1, 1, 1 } };
 
 static void estimate_normal(const or_fractal* f, const double p[3], double eps, int mode,
                             const double dir[3], double nrm[3], int64_t* evals, int64_t* bodies) {
@@ -398,6 +522,20 @@ static void estimate_normal(const or_fractal* f, const double p[3], double eps, 
     double l = sqrt(dot3(g, g));
     if (l == 0.0) { nrm[0] = -dir[0]; nrm[1] = -dir[1]; nrm[2] = -dir[2]; return; }
     nrm[0] = g[0] / l; nrm[1] = g[1] / l; nrm[2] = g[2] / l;
+}
+
+/* Normal (R10) at given points with a given eps, for parity checks that
+ * separate depth error from normal error.  dirs gives the fallback for a
+ * zero gradient.                                                            */
+void oracle_normal_at(const or_fractal* f, const double* pts, const double* dirs, const double* eps, int64_t n,
+                      int32_t mode, double* out) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t ev = 0, bo = 0;
+        estimate_normal(f, pts + 3 * i, eps[i], mode, dirs + 3 * i, out + 3 * i, &ev, &bo);
+    }
 }
 
 /* ------------------------------------------------------------------------ */

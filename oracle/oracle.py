@@ -86,6 +86,10 @@ def lib():
                                             dp, P(ctypes.c_int32)]
         L.oracle_pixel_jacobian.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int32
+        L.oracle_escape_margin.argtypes = [P(Fractal), dp, ctypes.c_int64, dp, P(ctypes.c_int32)]
+        L.oracle_normal_perturbed.argtypes = [P(Fractal), dp, dp, dp, ctypes.c_int64, ctypes.c_int32,
+                                              ctypes.c_double, ctypes.c_uint64, dp]
+        L.oracle_normal_at.argtypes = [P(Fractal), dp, dp, dp, ctypes.c_int64, ctypes.c_int32, dp]
         _lib = L
     return _lib
 
@@ -232,3 +236,57 @@ def camera_rays(camera, pixels):
                             _ptr(oo, ctypes.c_double), _ptr(dd, ctypes.c_double))
         o[k], d[k] = oo, dd
     return o, d
+
+
+def normal_at(fractal, points, dirs, eps, mode):
+    """Normal estimate (tetra or central taps) at points [n,3] with per-point eps."""
+    L = lib()
+    fr = make_fractal(fractal)
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    drs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    ep = np.ascontiguousarray(np.broadcast_to(eps, (pts.shape[0],)), dtype=np.float64)
+    out = np.empty_like(pts)
+    m = {"tetra": 0, "central": 1}[mode] if isinstance(mode, str) else int(mode)
+    L.oracle_normal_at(ctypes.byref(fr), _ptr(pts, ctypes.c_double), _ptr(drs, ctypes.c_double),
+                       _ptr(ep, ctypes.c_double), pts.shape[0], m, _ptr(out, ctypes.c_double))
+    return out
+
+
+def escape_margin(fractal, points):
+    """Smallest relative distance of |z_k|^2 to the bailout over the orbit at
+    each point [n,3], and whether the orbit escaped."""
+    L = lib()
+    fr = make_fractal(fractal)
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    m = np.empty(pts.shape[0])
+    e = np.empty(pts.shape[0], np.int32)
+    L.oracle_escape_margin(ctypes.byref(fr), _ptr(pts, ctypes.c_double), pts.shape[0], _ptr(m, ctypes.c_double),
+                           _ptr(e, ctypes.c_int32))
+    return m, e.astype(bool)
+
+
+TETRA_TAPS = np.array([[1, -1, -1], [-1, -1, 1], [-1, 1, -1], [1, 1, 1]], dtype=np.float64)
+CENTRAL_TAPS = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], dtype=np.float64)
+
+
+def tap_points(points, eps, mode):
+    """Normal-tap positions [n, taps, 3] around points [n,3] for per-point eps."""
+    m = {"tetra": 0, "central": 1}[mode] if isinstance(mode, str) else int(mode)
+    taps, h = (TETRA_TAPS, 0.5773 * np.asarray(eps)) if m == 0 else (CENTRAL_TAPS, np.asarray(eps))
+    return np.asarray(points)[:, None, :] + np.asarray(h).reshape(-1, 1, 1) * taps[None]
+
+
+def normal_perturbed(fractal, points, dirs, eps, mode, rel, seed):
+    """Normal at points with every orbit body perturbed by a relative
+    uniform(-rel, rel) factor per component (seeded): a rounding probe."""
+    L = lib()
+    fr = make_fractal(fractal)
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    drs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    ep = np.ascontiguousarray(np.broadcast_to(eps, (pts.shape[0],)), dtype=np.float64)
+    out = np.empty_like(pts)
+    m = {"tetra": 0, "central": 1}[mode] if isinstance(mode, str) else int(mode)
+    L.oracle_normal_perturbed(ctypes.byref(fr), _ptr(pts, ctypes.c_double), _ptr(drs, ctypes.c_double),
+                              _ptr(ep, ctypes.c_double), pts.shape[0], m, float(rel), int(seed),
+                              _ptr(out, ctypes.c_double))
+    return out
