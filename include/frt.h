@@ -1,0 +1,234 @@
+/*
+ * frt.h -- C ABI of the MI355X fractal sphere tracer.
+ *
+ * Renders escape-time fractals by per-pixel sphere tracing, after da Silva,
+ * Novello, Lopes and Velho, "Real-time rendering of complex fractals"
+ * (arXiv 2102.01747):
+ *   - the quaternion Julia set z^2 + c (Sec. 1.1), sliced to 3-D with the
+ *     fourth quaternion component zero and optionally cut by planes (Fig. 1
+ *     and the text around Listing 3);
+ *   - the White-Nylander power-n Mandelbulb (Sec. 1.2, Eq. 1, Listing 7).
+ * Both are driven by the orbit-derivative distance estimate
+ * d = 0.5 |z| ln|z| / |z'| (Sec. 2, Eq. 2-4; Listings 4 and 7), marched as in
+ * Listing 3, with normals from distance taps (Eq. 5, Listing 5) and Lambert
+ * shading with an optional shadow ray.
+ *
+ * Conventions shared by every entry point
+ *   - All device buffers are owned by the caller.  The library keeps no
+ *     pointer after a call returns, except that a captured batch graph
+ *     (frt_render_batch with use_graph=1) keeps the workspace pointer until
+ *     frt_graph_reset() or the next capture.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL is the
+ *     default stream).  Device faults surface at the caller's next sync.
+ *   - Parameter structs are read by value during the call.
+ *   - Invalid arguments return FRT_EINVAL before anything is launched, so
+ *     no output is written; frt_last_error() then names the argument.
+ *   - No C++ exception crosses this interface.
+ *
+ * Framebuffer layout (frt_frame): structure of arrays over P = width*height
+ * pixels, linear index j*width + i with row j = 0 at the top of the image.
+ *   depth    float[P]      ray parameter t* of the hit along the unit ray
+ *                          direction (Euclidean distance from the eye),
+ *                          -1 on a miss
+ *   normal   float[3][P]   unit normal planes x, y, z (0 on a miss)
+ *   colour   float[3][P]   shaded colour planes r, g, b (0 on a miss)
+ *   status   uint8[P]      bits 0-2: 0 miss (no bounding interval),
+ *                          1 miss (left the interval), 2 hit, 3 hit on a cut
+ *                          face, 4 hit by running out of steps;
+ *                          bit 3: shadowed (the shadow ray hit);
+ *                          bit 4: depth not refined (first sample or
+ *                          running out of steps)
+ *   counters uint32[4][P]  optional (NULL to skip): primary march samples,
+ *                          distance evaluations in total, orbit bodies in
+ *                          total, escape count at the last march sample
+ */
+#ifndef FRT_H
+#define FRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FRT_OK = 0,
+    FRT_EINVAL = -1,        /* invalid argument; nothing launched            */
+    FRT_EHIP = -2,          /* a HIP runtime call failed                     */
+    FRT_ENOMEM = -3,        /* workspace too small                           */
+    FRT_EUNSUPPORTED = -4   /* valid request this build cannot serve         */
+} frt_status;
+
+enum { FRT_JULIA = 0, FRT_MANDELBULB = 1 };
+enum { FRT_NORMAL_TETRA = 0, FRT_NORMAL_CENTRAL = 1 };
+
+/* Pinhole camera: vertical field of view, pixel centres, row 0 at the top.
+ * Ray through pixel (i, j): dir = normalize(f + x r + y u) with
+ * f = normalize(target - eye), r = normalize(f x up), u = r x f,
+ * s = tan(fov_y/2), x = (2(i+1/2)/W - 1) s W/H, y = (1 - 2(j+1/2)/H) s.     */
+typedef struct {
+    float eye[3], target[3], up[3];
+    float fov_y_deg;            /* (0, 180)                                  */
+    int32_t width, height;      /* >= 1 each                                 */
+} frt_camera;
+
+/* Fractal (Sec. 1.1, 1.2).  Julia: z0 = (x, y, z, 0) with component 0 the
+ * real part, z <- z^2 + c (Eq. 3).  Mandelbulb: w0 = p, w <- w^n + p with the
+ * power map of Eq. 1 in Listing 7's axes (y polar, azimuth atan2(x, z)),
+ * any real n >= 2.  An orbit stops after max_iter bodies or when |z|^2
+ * exceeds bailout2.  The march is confined to a sphere whose radius is the
+ * larger of the provable escape radius ((1 + sqrt(1 + 4|c|))/2 for Julia,
+ * 2^(1/(n-1)) for the Mandelbulb) and bound_radius (0 for automatic).      */
+typedef struct {
+    int32_t kind;               /* FRT_JULIA or FRT_MANDELBULB               */
+    float c[4];                 /* Julia constant; ignored for Mandelbulb    */
+    float power;                /* Mandelbulb n >= 2; ignored for Julia      */
+    int32_t max_iter;           /* [1, 4096]                                 */
+    float bailout2;             /* > 0                                       */
+    float bound_radius;         /* >= 0                                      */
+} frt_fractal;
+
+/* Cut plane: the kept half-space is { x : (n/|n|) . x <= d }.  n need not be
+ * unit length (it must be non-zero); gradients are taken w.r.t. raw n.     */
+typedef struct {
+    float n[3];
+    float d;
+} frt_plane;
+
+/* March and shading (Listing 3, Eq. 5, Listing 5).
+ * eps(t) = eps_abs + eps_rel t is the stop threshold; steps are
+ * min(d, step_clamp); the search interval starts at eps_abs and ends at
+ * t_max, cut by the bounding sphere and the planes.  A hit is refined to the
+ * root of d - eps(t) between the last two samples by bisection (at most
+ * refine_iters halvings, stopping once the bracket is narrower than
+ * eps(t)/32) and one secant step on the final bracket; bisection picks the
+ * same root as the FP64 reference when the bracket holds several (the
+ * estimate jumps where the escape count changes).  Normals: tetrahedral taps with
+ * h = 0.5773 eps(t*) or central differences with h = eps(t*).
+ * colour = albedo (k_ambient + k_diffuse max(0, N.L) V), L = light_dir
+ * normalised, V = 0 when the shadow ray (from p* + 4 eps(t*) N toward L,
+ * threshold eps(t*)) hits, else 1; V is traced only when shadow != 0 and
+ * N.L > 0.                                                                 */
+typedef struct {
+    int32_t max_steps;          /* [1, 65536]                                */
+    float eps_abs, eps_rel;     /* >= 0, not both 0                          */
+    float step_clamp;           /* > 0                                       */
+    float t_max;                /* > eps_abs                                 */
+    int32_t normal_mode;        /* FRT_NORMAL_TETRA or FRT_NORMAL_CENTRAL    */
+    int32_t refine_iters;       /* [0, 32]                                   */
+    int32_t shadow;             /* 0 or 1                                    */
+    float light_dir[3];         /* non-zero                                  */
+    float albedo[3];
+    float k_ambient, k_diffuse;
+} frt_march;
+
+/* Output planes (device pointers, see the layout above).  depth, normal,
+ * colour and status are required; counters may be NULL.                   */
+typedef struct {
+    float* depth;
+    float* normal;
+    float* colour;
+    uint8_t* status;
+    uint32_t* counters;
+} frt_frame;
+
+/* One render of a batch. */
+typedef struct {
+    frt_camera cam;
+    frt_fractal frac;
+    frt_plane planes[2];
+    int32_t n_planes;           /* [0, 2]                                    */
+    frt_march march;
+    frt_frame out;
+} frt_job;
+
+/* Device workspace needed by a call over n_jobs renders (job table and ray
+ * queue counters).  Any device allocation of at least this many bytes,
+ * 256-byte aligned, serves.                                                 */
+size_t frt_workspace_bytes(int32_t n_jobs);
+
+/* Render one view (the per-pixel path of Listings 2-5 and 7).
+ * workspace: device memory of frt_workspace_bytes(1) bytes (ws_bytes).
+ * Returns FRT_EINVAL (nothing launched) for invalid parameters, FRT_ENOMEM
+ * when the workspace is too small, FRT_EHIP when a launch fails.           */
+frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_plane* planes,
+                      int32_t n_planes, const frt_march* march, frt_frame out,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* Render n_jobs independent views in one persistent launch: the rays of all
+ * jobs form one index space that waves drain through a shared queue.
+ * jobs: host array of n_jobs (>= 1) entries; workspace: device memory of
+ * frt_workspace_bytes(n_jobs) bytes.  use_graph = 1 replays a HIP graph of
+ * the launch captured on the first call with the same (workspace, stream,
+ * job kinds); the job table is re-uploaded before every replay, so
+ * parameters and output pointers may change between calls.
+ * Errors as frt_render; a job's index appears in frt_last_error().         */
+frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace, size_t ws_bytes,
+                            int32_t use_graph, void* stream);
+
+/* Adjoint of a batch render by implicit differentiation at the hit points:
+ * for a refined hit, d t* / d theta = -(dd/dtheta) / (grad d . dir - eps_rel);
+ * normal and colour follow by the chain rule through the normal taps, whose
+ * orbit tangents are recomputed (nothing from the forward orbit is stored).
+ * Cut-face hits use t* = (d - n_hat.o)/(n_hat.dir) and normal n_hat.
+ * Exhausted and unrefined hits, misses and the shadow visibility contribute
+ * nothing.
+ * jobs: the forward jobs with out.depth and out.status from the forward
+ *       call (other out pointers unused);
+ * g_colour: host array of n_jobs device pointers, each float[3][P]
+ *       (required); g_depth (float[P]) and g_normal (float[3][P]) host
+ *       arrays may be NULL, as may any of their entries;
+ * grad_c [n_jobs][4], grad_power [n_jobs], grad_plane [n_jobs][2][4] (raw
+ *       n xyz, d): device float outputs, overwritten (zeroed, then
+ *       accumulated with atomics, so the last bits vary run to run).
+ * workspace: frt_workspace_bytes(n_jobs) bytes.                            */
+frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float* const* g_colour,
+                               const float* const* g_depth, const float* const* g_normal,
+                               float* grad_c, float* grad_power, float* grad_plane,
+                               void* workspace, size_t ws_bytes, void* stream);
+
+/* Distance estimate (Sec. 2, Eq. 2-4) at n points, the same orbit code the
+ * renderer marches with: points float[n][3] (device), d float[n] (device),
+ * iters int32[n] (device, may be NULL) receives the escape count (max_iter:
+ * no escape).  frac is validated as for frt_render.                        */
+frt_status frt_distance(const frt_fractal* frac, const float* points, int64_t n, float* d, int32_t* iters,
+                        void* stream);
+
+/* Evaluate one of the library's fast float32 functions on n device values,
+ * for accuracy checks: func 0 acos(x) (x clamped to [-1, 1]), 1 atan2(x, y),
+ * 2 sin(2 pi x), 3 cos(2 pi x), 4 log2(x), 5 exp2(x), 6 1/sqrt(x), 7 1/x.
+ * y is read only by func 1.                                                 */
+frt_status frt_math_eval(int32_t func, const float* x, const float* y, float* out, int64_t n, void* stream);
+
+/* Launch configuration of the persistent kernels, chosen by the autotuner.
+ * kernel_variant: 0 Julia, 1 Mandelbulb (real n), 2 Mandelbulb (integer n),
+ * 3 mixed kinds, 4 Mandelbulb with n = 8 (the power the paper renders).
+ * block: 64, 128, 256 or 512 threads; chunk: rays taken from the queue per
+ * refill, a multiple of 64 in [64, 4096]; waves_per_simd: resident waves per
+ * SIMD the grid is sized for, [1, 8] (0 = occupancy limit);
+ * bodies_per_trip: orbit bodies a lane advances per trip of the wave loop
+ * before lanes whose estimate is done take their next step, [1, 64];
+ * rare_lanes: number of waiting lanes that triggers shading, output writes
+ * and refill, [1, 64].  The setting is process-wide and applies to launches
+ * that start after the call.                                               */
+frt_status frt_autotune_set(int32_t kernel_variant, int32_t block, int32_t chunk, int32_t waves_per_simd,
+                            int32_t bodies_per_trip, int32_t rare_lanes);
+frt_status frt_autotune_get(int32_t kernel_variant, int32_t* block, int32_t* chunk, int32_t* waves_per_simd,
+                            int32_t* bodies_per_trip, int32_t* rare_lanes);
+
+/* Drop every captured batch graph; the next graph call captures again.     */
+frt_status frt_graph_reset(void);
+
+/* Static description of a status code.                                     */
+const char* frt_status_string(frt_status s);
+
+/* Message of the last failed call on this thread (empty if none); valid
+ * until the next frt_* call on the same thread.                            */
+const char* frt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRT_H */

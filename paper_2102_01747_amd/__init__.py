@@ -1,0 +1,251 @@
+"""MI355X fractal sphere tracer -- Python binding of libfrt.so.
+
+Argument marshalling only: every step of a render (ray generation, bounding
+interval, cut face, march, refinement, normals, shading, shadow ray, adjoint)
+runs in the HIP kernels of libfrt.so.  PyTorch supplies device memory and the
+stream.  Jobs are the plain dictionaries of ``workloads.py``.
+
+The library must have been built (``python -m paper_2102_01747_amd._build``
+or ``__graft_entry__.build()``); importing the functions below without it
+raises ``FrtError``.
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfrt.so")
+
+FRT_OK, FRT_EINVAL, FRT_EHIP, FRT_ENOMEM, FRT_EUNSUPPORTED = 0, -1, -2, -3, -4
+STATUS_MISS_BOUNDS, STATUS_MISS_TMAX, STATUS_HIT, STATUS_HIT_CUT, STATUS_HIT_EXHAUSTED = 0, 1, 2, 3, 4
+FLAG_SHADOWED, FLAG_UNREFINED = 8, 16
+VARIANTS = {"julia": 0, "bulb_real": 1, "bulb_int": 2, "mixed": 3, "bulb8": 4}
+
+f3 = ctypes.c_float * 3
+f4 = ctypes.c_float * 4
+
+
+class FrtError(RuntimeError):
+    pass
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", f3), ("target", f3), ("up", f3), ("fov_y_deg", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class Fractal(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("c", f4), ("power", ctypes.c_float), ("max_iter", ctypes.c_int32),
+                ("bailout2", ctypes.c_float), ("bound_radius", ctypes.c_float)]
+
+
+class Plane(ctypes.Structure):
+    _fields_ = [("n", f3), ("d", ctypes.c_float)]
+
+
+class March(ctypes.Structure):
+    _fields_ = [("max_steps", ctypes.c_int32), ("eps_abs", ctypes.c_float), ("eps_rel", ctypes.c_float),
+                ("step_clamp", ctypes.c_float), ("t_max", ctypes.c_float), ("normal_mode", ctypes.c_int32),
+                ("refine_iters", ctypes.c_int32), ("shadow", ctypes.c_int32), ("light_dir", f3), ("albedo", f3),
+                ("k_ambient", ctypes.c_float), ("k_diffuse", ctypes.c_float)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_void_p), ("normal", ctypes.c_void_p), ("colour", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("counters", ctypes.c_void_p)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("cam", Camera), ("frac", Fractal), ("planes", Plane * 2), ("n_planes", ctypes.c_int32),
+                ("march", March), ("out", Frame)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libfrt.so; raises FrtError when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FrtError("libfrt.so is not built (%s); run paper_2102_01747_amd._build.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        P = ctypes.POINTER
+        L.frt_workspace_bytes.argtypes = [i32]
+        L.frt_workspace_bytes.restype = sz
+        L.frt_render.argtypes = [P(Camera), P(Fractal), P(Plane), i32, P(March), Frame, vp, sz, vp]
+        L.frt_render.restype = ctypes.c_int
+        L.frt_render_batch.argtypes = [P(Job), i32, vp, sz, i32, vp]
+        L.frt_render_batch.restype = ctypes.c_int
+        L.frt_render_backward.argtypes = [P(Job), i32, P(vp), P(vp), P(vp), vp, vp, vp, vp, sz, vp]
+        L.frt_render_backward.restype = ctypes.c_int
+        L.frt_autotune_set.argtypes = [i32, i32, i32, i32, i32, i32]
+        L.frt_autotune_set.restype = ctypes.c_int
+        L.frt_autotune_get.argtypes = [i32, P(i32), P(i32), P(i32), P(i32), P(i32)]
+        L.frt_autotune_get.restype = ctypes.c_int
+        L.frt_graph_reset.argtypes = []
+        L.frt_graph_reset.restype = ctypes.c_int
+        L.frt_distance.argtypes = [P(Fractal), vp, ctypes.c_int64, vp, vp, vp]
+        L.frt_distance.restype = ctypes.c_int
+        L.frt_math_eval.argtypes = [i32, vp, vp, vp, ctypes.c_int64, vp]
+        L.frt_math_eval.restype = ctypes.c_int
+        L.frt_status_string.argtypes = [ctypes.c_int]
+        L.frt_status_string.restype = ctypes.c_char_p
+        L.frt_last_error.argtypes = []
+        L.frt_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != FRT_OK:
+        L = lib()
+        raise FrtError("%s: %s" % (L.frt_status_string(status).decode(), L.frt_last_error().decode()))
+
+
+# --------------------------------------------------------------- marshalling
+def make_camera(cam):
+    return Camera(f3(*cam["eye"]), f3(*cam["target"]), f3(*cam["up"]), float(cam["fov_y_deg"]),
+                  int(cam["width"]), int(cam["height"]))
+
+
+def make_fractal(fr):
+    kind = {"julia": 0, "bulb": 1}[fr["kind"]] if isinstance(fr["kind"], str) else int(fr["kind"])
+    return Fractal(kind, f4(*fr.get("c", (0.0, 0.0, 0.0, 0.0))), float(fr.get("power", 2.0)), int(fr["max_iter"]),
+                   float(fr["bailout2"]), float(fr.get("bound_radius", 0.0)))
+
+
+def make_planes(planes):
+    arr = (Plane * 2)()
+    for k, pl in enumerate(planes):
+        arr[k] = Plane(f3(*pl["n"]), float(pl["d"]))
+    return arr, len(planes)
+
+
+def make_march(m):
+    mode = {"tetra": 0, "central": 1}[m["normal_mode"]] if isinstance(m["normal_mode"], str) else int(m["normal_mode"])
+    return March(int(m["max_steps"]), float(m["eps_abs"]), float(m["eps_rel"]), float(m["step_clamp"]),
+                 float(m["t_max"]), mode, int(m.get("refine_iters", 12)), int(bool(m["shadow"])),
+                 f3(*m["light_dir"]), f3(*m["albedo"]), float(m["k_ambient"]), float(m["k_diffuse"]))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _device(device):
+    d = torch.device(device)
+    if d.type != "cuda":
+        raise FrtError("the renderer runs on a GPU device, got %s" % d)
+    return d
+
+
+def alloc_frame(job, device="cuda", counters=False):
+    """Output planes of one job (see include/frt.h for the layout)."""
+    cam = job["camera"]
+    P = int(cam["width"]) * int(cam["height"])
+    dev = _device(device)
+    fr = {"depth": torch.empty(P, device=dev, dtype=torch.float32),
+          "normal": torch.empty(3, P, device=dev, dtype=torch.float32),
+          "colour": torch.empty(3, P, device=dev, dtype=torch.float32),
+          "status": torch.empty(P, device=dev, dtype=torch.uint8)}
+    if counters:
+        fr["counters"] = torch.empty(4, P, device=dev, dtype=torch.int32)   # read as uint32
+    return fr
+
+
+def make_frame(fr):
+    return Frame(_ptr(fr["depth"]), _ptr(fr["normal"]), _ptr(fr["colour"]), _ptr(fr["status"]),
+                 _ptr(fr.get("counters")))
+
+
+def workspace_bytes(n_jobs):
+    return int(lib().frt_workspace_bytes(int(n_jobs)))
+
+
+def alloc_workspace(n_jobs, device="cuda"):
+    ws = torch.empty(workspace_bytes(n_jobs) + 256, device=_device(device), dtype=torch.uint8)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + workspace_bytes(n_jobs)]
+
+
+def make_job(job, frame):
+    pl, npl = make_planes(job.get("planes", []))
+    return Job(make_camera(job["camera"]), make_fractal(job["fractal"]), pl, npl, make_march(job["march"]),
+               make_frame(frame))
+
+
+# ------------------------------------------------------------------- render
+def render(job, device="cuda", counters=False, out=None, workspace=None):
+    """Render one job asynchronously on the current stream; returns the
+    frame dict (depth, normal, colour, status[, counters])."""
+    L = lib()
+    dev = _device(device)
+    fr = out if out is not None else alloc_frame(job, dev, counters)
+    ws = workspace if workspace is not None else alloc_workspace(1, dev)
+    pl, npl = make_planes(job.get("planes", []))
+    cam, frac, mc = make_camera(job["camera"]), make_fractal(job["fractal"]), make_march(job["march"])
+    _check(L.frt_render(ctypes.byref(cam), ctypes.byref(frac), pl, npl, ctypes.byref(mc), make_frame(fr),
+                        _ptr(ws), ws.numel(), _stream(dev)))
+    return fr
+
+
+def render_batch(jobs, device="cuda", counters=False, use_graph=False, outs=None, workspace=None):
+    """Render many jobs in one persistent launch; returns a list of frames."""
+    L = lib()
+    dev = _device(device)
+    frames = outs if outs is not None else [alloc_frame(j, dev, counters) for j in jobs]
+    ws = workspace if workspace is not None else alloc_workspace(len(jobs), dev)
+    arr = (Job * len(jobs))(*[make_job(j, f) for j, f in zip(jobs, frames)])
+    _check(L.frt_render_batch(arr, len(jobs), _ptr(ws), ws.numel(), int(bool(use_graph)), _stream(dev)))
+    return frames
+
+
+def distance(fractal, points, device="cuda"):
+    """Distance estimate and escape count at points [n, 3] (a CUDA float32
+    tensor, or anything torch.as_tensor accepts)."""
+    dev = _device(device)
+    pts = torch.as_tensor(points, dtype=torch.float32, device=dev).reshape(-1, 3).contiguous()
+    n = pts.shape[0]
+    d = torch.empty(n, device=dev, dtype=torch.float32)
+    it = torch.empty(n, device=dev, dtype=torch.int32)
+    frac = make_fractal(fractal)
+    _check(lib().frt_distance(ctypes.byref(frac), _ptr(pts), n, _ptr(d), _ptr(it), _stream(dev)))
+    return d, it
+
+
+MATH_FUNCS = {"acos": 0, "atan2": 1, "sin_rev": 2, "cos_rev": 3, "log2": 4, "exp2": 5, "rsq": 6, "rcp": 7}
+
+
+def math_eval(func, x, y=None, device="cuda"):
+    """The library's fast float32 function `func` (see MATH_FUNCS) on x (and y)."""
+    dev = _device(device)
+    xs = torch.as_tensor(x, dtype=torch.float32, device=dev).contiguous()
+    ys = torch.as_tensor(y, dtype=torch.float32, device=dev).contiguous() if y is not None else None
+    out = torch.empty_like(xs)
+    _check(lib().frt_math_eval(MATH_FUNCS[func], _ptr(xs), _ptr(ys), _ptr(out), xs.numel(), _stream(dev)))
+    return out
+
+
+def autotune_set(variant, block, chunk, waves_per_simd=0, bodies_per_trip=1, rare_lanes=16):
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    _check(lib().frt_autotune_set(v, int(block), int(chunk), int(waves_per_simd), int(bodies_per_trip),
+                                  int(rare_lanes)))
+
+
+def autotune_get(variant):
+    """(block, chunk, waves_per_simd, bodies_per_trip, rare_lanes) of a kernel variant."""
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    vals = [ctypes.c_int32() for _ in range(5)]
+    _check(lib().frt_autotune_get(v, *[ctypes.byref(x) for x in vals]))
+    return tuple(x.value for x in vals)
+
+
+def graph_reset():
+    _check(lib().frt_graph_reset())

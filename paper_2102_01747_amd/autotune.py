@@ -1,0 +1,121 @@
+"""Autotuner for the persistent trace kernels.
+
+For a list of jobs (rendered as one batch launch, or one launch per job),
+searches the launch configuration of the kernel variant the jobs use --
+block size, rays claimed per queue refill (chunk), resident waves per SIMD
+the grid is sized for, orbit bodies per loop trip and the number of waiting
+lanes that triggers shading/refill -- by coordinate descent from the current
+setting, timing each candidate with HIP events on the current stream (median
+of `reps` launches after one warm-up).  The best setting is installed with
+frt_autotune_set and can be cached in a JSON file keyed by variant and a
+workload tag.
+"""
+import json
+import os
+import statistics
+
+import torch
+
+from . import VARIANTS, alloc_frame, alloc_workspace, autotune_get, autotune_set, render, render_batch
+
+SPACE = {
+    "block": [64, 128, 256, 512],
+    "chunk": [64, 128, 256, 512, 1024],
+    "waves_per_simd": [1, 2, 3, 4, 0],
+    "bodies_per_trip": [1, 2, 3, 4, 6, 10],
+    "rare_lanes": [2, 4, 8, 16, 32, 48],
+}
+KEYS = ["block", "chunk", "waves_per_simd", "bodies_per_trip", "rare_lanes"]
+
+
+def variant_of(jobs):
+    """Kernel variant the library picks for these jobs."""
+    kinds = set()
+    for j in jobs:
+        fr = j["fractal"]
+        if fr["kind"] == "julia":
+            kinds.add("julia")
+        else:
+            n = float(fr["power"])
+            kinds.add("bulb8" if n == 8.0 else ("bulb_int" if n.is_integer() and 2 <= n <= 64 else "bulb_real"))
+    return kinds.pop() if len(kinds) == 1 else "mixed"
+
+
+def time_config(jobs, frames, ws, batch, reps=5, device="cuda"):
+    stream = torch.cuda.current_stream(device)
+
+    def launch():
+        if batch:
+            render_batch(jobs, device, outs=frames, workspace=ws)
+        else:
+            for j, f in zip(jobs, frames):
+                render(j, device, out=f, workspace=ws)
+
+    launch()
+    times = []
+    for _ in range(reps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        launch()
+        e.record(stream)
+        e.synchronize()
+        times.append(s.elapsed_time(e))
+    return statistics.median(times)
+
+
+def tune(jobs, batch=True, reps=5, passes=2, device="cuda", log=None):
+    """Coordinate descent over SPACE; installs and returns the best config
+    as a dict together with its time in ms."""
+    var = variant_of(jobs)
+    frames = [alloc_frame(j, device) for j in jobs]
+    ws = alloc_workspace(len(jobs), device)
+    cur = dict(zip(KEYS, autotune_get(var)))
+    timed = {}
+
+    def measure(cfg):
+        key = tuple(cfg[k] for k in KEYS)
+        if key not in timed:
+            autotune_set(var, *key)
+            timed[key] = time_config(jobs, frames, ws, batch, reps, device)
+            if log:
+                log("  %s %.3f ms" % (dict(zip(KEYS, key)), timed[key]))
+        return timed[key]
+
+    best = measure(cur)
+    for _ in range(passes):
+        improved = False
+        for k in KEYS:
+            for v in SPACE[k]:
+                cand = dict(cur, **{k: v})
+                t = measure(cand)
+                if t < best * 0.995:
+                    best, cur, improved = t, cand, True
+        if not improved:
+            break
+    autotune_set(var, *[cur[k] for k in KEYS])
+    return {"variant": var, "config": cur, "ms": best, "candidates": len(timed)}
+
+
+def load_cache(path, tag):
+    """Install cached settings for `tag` (if the file has them)."""
+    if not os.path.exists(path):
+        return False
+    with open(path) as fh:
+        data = json.load(fh)
+    entry = data.get(tag)
+    if not entry:
+        return False
+    for var, cfg in entry.items():
+        if var in VARIANTS:
+            autotune_set(var, *[cfg[k] for k in KEYS])
+    return True
+
+
+def save_cache(path, tag, result):
+    data = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            data = json.load(fh)
+    data.setdefault(tag, {})[result["variant"]] = result["config"]
+    with open(path, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)

@@ -1,0 +1,525 @@
+// frt_api.cpp -- host side of the C ABI declared in include/frt.h:
+// argument validation, packing of public jobs into device descriptors,
+// persistent-grid sizing, batch graph capture and the autotune table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "frt.h"
+#include "frt_fractal.hpp"
+#include "frt_internal.hpp"
+#include "frt_job.hpp"
+
+using frt::JobDev;
+using frt::LaunchCfg;
+using frt::WorkspaceHeader;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+frt_status fail(frt_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+frt_status hip_fail(hipError_t e, const char* what) {
+    return fail(FRT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- tuning
+struct Tune {
+    int block;
+    int chunk;
+    int waves_per_simd;
+    int bodies_per_trip;
+    int rare_lanes;
+};
+std::mutex g_mu;
+Tune g_tune[frt::kNumVariants] = {
+    {128, 64, 0, 6, 16},   // Julia
+    {128, 64, 0, 6, 16},   // Mandelbulb, real power
+    {128, 64, 0, 6, 16},   // Mandelbulb, integer power
+    {128, 64, 0, 6, 16},   // mixed
+    {128, 64, 0, 6, 16},   // Mandelbulb, n = 8
+};
+
+int device_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cached[dev] = n;
+    }
+    return cached[dev];
+}
+
+bool make_cfg(const void* kernel, int variant, LaunchCfg& cfg, std::string& why) {
+    Tune t;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        t = g_tune[variant];
+    }
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, t.block, 0);
+    if (e != hipSuccess || per_cu <= 0) {
+        why = std::string("occupancy query failed: ") + hipGetErrorString(e);
+        return false;
+    }
+    if (t.waves_per_simd > 0) {
+        const int want = (t.waves_per_simd * 4 * 64) / t.block;   // 4 SIMDs per CU
+        per_cu = std::max(1, std::min(per_cu, want));
+    }
+    cfg.grid = per_cu * device_cus();
+    cfg.normal_grid = 8 * device_cus();
+    cfg.block = t.block;
+    cfg.chunk = t.chunk;
+    cfg.bodies_per_trip = t.bodies_per_trip;
+    cfg.rare_lanes = t.rare_lanes;
+    return true;
+}
+
+// ------------------------------------------------------------ validation
+bool finite(float x) { return std::isfinite(x); }
+bool finite_n(const float* v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!finite(v[i])) return false;
+    return true;
+}
+double norm3(const float* v) {
+    return std::sqrt(double(v[0]) * v[0] + double(v[1]) * v[1] + double(v[2]) * v[2]);
+}
+
+bool validate(const frt_camera* cam, const frt_fractal* fr, const frt_plane* planes, int32_t n_planes,
+              const frt_march* mc, const frt_frame* out, bool need_outputs, std::string& why) {
+    if (!cam || !fr || !mc) { why = "null parameter block"; return false; }
+    if (cam->width < 1 || cam->height < 1) { why = "width and height must be >= 1"; return false; }
+    if ((long long)cam->width * cam->height > (1ll << 31) - 1) { why = "image larger than 2^31 pixels"; return false; }
+    if (!finite_n(cam->eye, 3) || !finite_n(cam->target, 3) || !finite_n(cam->up, 3) || !finite(cam->fov_y_deg)) {
+        why = "non-finite camera"; return false;
+    }
+    if (!(cam->fov_y_deg > 0.0f && cam->fov_y_deg < 180.0f)) { why = "fov_y_deg must be in (0, 180)"; return false; }
+    const float f[3] = {cam->target[0] - cam->eye[0], cam->target[1] - cam->eye[1], cam->target[2] - cam->eye[2]};
+    const double fl = norm3(f);
+    if (!(fl > 0.0)) { why = "eye and target coincide"; return false; }
+    const double c0 = double(f[1]) * cam->up[2] - double(f[2]) * cam->up[1];
+    const double c1 = double(f[2]) * cam->up[0] - double(f[0]) * cam->up[2];
+    const double c2 = double(f[0]) * cam->up[1] - double(f[1]) * cam->up[0];
+    if (!(std::sqrt(c0 * c0 + c1 * c1 + c2 * c2) > 1e-12 * fl * norm3(cam->up))) {
+        why = "up is parallel to the view direction"; return false;
+    }
+    if (fr->kind != FRT_JULIA && fr->kind != FRT_MANDELBULB) { why = "unknown fractal kind"; return false; }
+    if (!finite_n(fr->c, 4) || !finite(fr->power) || !finite(fr->bailout2) || !finite(fr->bound_radius)) {
+        why = "non-finite fractal parameter"; return false;
+    }
+    if (fr->max_iter < 1 || fr->max_iter > 4096) { why = "max_iter must be in [1, 4096]"; return false; }
+    if (!(fr->bailout2 > 0.0f)) { why = "bailout2 must be > 0"; return false; }
+    if (!(fr->bound_radius >= 0.0f)) { why = "bound_radius must be >= 0"; return false; }
+    if (fr->kind == FRT_MANDELBULB && !(fr->power >= 2.0f)) { why = "Mandelbulb power must be >= 2"; return false; }
+    if (n_planes < 0 || n_planes > 2) { why = "n_planes must be in [0, 2]"; return false; }
+    if (n_planes > 0 && !planes) { why = "planes is null"; return false; }
+    for (int k = 0; k < n_planes; ++k) {
+        if (!finite_n(planes[k].n, 3) || !finite(planes[k].d)) { why = "non-finite plane"; return false; }
+        if (!(norm3(planes[k].n) > 0.0)) { why = "plane normal is zero"; return false; }
+    }
+    if (mc->max_steps < 1 || mc->max_steps > 65536) { why = "max_steps must be in [1, 65536]"; return false; }
+    if (!finite(mc->eps_abs) || !finite(mc->eps_rel) || !finite(mc->step_clamp) || !finite(mc->t_max) ||
+        !finite_n(mc->light_dir, 3) || !finite_n(mc->albedo, 3) || !finite(mc->k_ambient) || !finite(mc->k_diffuse)) {
+        why = "non-finite march parameter"; return false;
+    }
+    if (mc->eps_abs < 0.0f || mc->eps_rel < 0.0f || (mc->eps_abs == 0.0f && mc->eps_rel == 0.0f)) {
+        why = "eps_abs and eps_rel must be >= 0 and not both 0"; return false;
+    }
+    if (!(mc->step_clamp > 0.0f)) { why = "step_clamp must be > 0"; return false; }
+    if (!(mc->t_max > mc->eps_abs)) { why = "t_max must exceed eps_abs"; return false; }
+    if (mc->normal_mode != FRT_NORMAL_TETRA && mc->normal_mode != FRT_NORMAL_CENTRAL) {
+        why = "unknown normal_mode"; return false;
+    }
+    if (mc->refine_iters < 0 || mc->refine_iters > 32) { why = "refine_iters must be in [0, 32]"; return false; }
+    if (mc->shadow != 0 && mc->shadow != 1) { why = "shadow must be 0 or 1"; return false; }
+    if (!(norm3(mc->light_dir) > 0.0)) { why = "light_dir is zero"; return false; }
+    if (need_outputs) {
+        if (!out || !out->depth || !out->normal || !out->colour || !out->status) {
+            why = "null output plane"; return false;
+        }
+    }
+    return true;
+}
+
+// --------------------------------------------------------------- packing
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+void pack(const frt_camera* cam, const frt_fractal* fr, const frt_plane* planes, int32_t n_planes,
+          const frt_march* mc, const frt_frame& out, int64_t ray_begin, JobDev& J) {
+    std::memset(&J, 0, sizeof(J));
+    // camera basis in double, rounded once
+    double f[3] = {double(cam->target[0]) - cam->eye[0], double(cam->target[1]) - cam->eye[1],
+                   double(cam->target[2]) - cam->eye[2]};
+    double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    for (double& v : f) v /= fl;
+    double r[3] = {f[1] * cam->up[2] - f[2] * cam->up[1], f[2] * cam->up[0] - f[0] * cam->up[2],
+                   f[0] * cam->up[1] - f[1] * cam->up[0]};
+    double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    for (double& v : r) v /= rl;
+    const double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+    const double s = std::tan(0.5 * double(cam->fov_y_deg) * M_PI / 180.0);
+    for (int k = 0; k < 3; ++k) {
+        J.eye[k] = cam->eye[k];
+        J.fwd[k] = float(f[k]);
+        J.right[k] = float(r[k]);
+        J.upv[k] = float(u[k]);
+    }
+    J.sx = float(s * cam->width / cam->height);
+    J.sy = float(s);
+    J.inv_w2 = float(2.0 / cam->width);
+    J.inv_h2 = float(2.0 / cam->height);
+    J.width = cam->width;
+    J.height = cam->height;
+    J.tiles_x = (cam->width + frt::kTile - 1) / frt::kTile;
+    J.tiles_y = (cam->height + frt::kTile - 1) / frt::kTile;
+    // fractal
+    J.kind = fr->kind;
+    J.max_iter = fr->max_iter;
+    J.bailout2 = fr->bailout2;
+    for (int k = 0; k < 4; ++k) J.c[k] = fr->kind == FRT_JULIA ? fr->c[k] : 0.0f;
+    double R;
+    if (fr->kind == FRT_JULIA) {
+        J.power = 2.0f;
+        const double cn = std::sqrt(double(fr->c[0]) * fr->c[0] + double(fr->c[1]) * fr->c[1] +
+                                    double(fr->c[2]) * fr->c[2] + double(fr->c[3]) * fr->c[3]);
+        R = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * cn));
+        J.int_power = 2;
+    } else {
+        J.power = fr->power;
+        R = std::pow(2.0, 1.0 / (double(fr->power) - 1.0));
+        const float ip = std::floor(fr->power);
+        J.int_power = (ip == fr->power && ip >= 2.0f && ip <= 64.0f) ? int(ip) : 0;
+    }
+    R = std::max(R, double(fr->bound_radius));
+    J.radius = float(R);
+    J.n_rev = float(double(J.power) / (2.0 * M_PI));
+    // planes
+    J.n_planes = n_planes;
+    for (int k = 0; k < n_planes; ++k) {
+        const double l = norm3(planes[k].n);
+        for (int e = 0; e < 3; ++e) J.pn[k][e] = float(planes[k].n[e] / l);
+        J.pd[k] = planes[k].d;
+    }
+    // march / shading
+    J.max_steps = mc->max_steps;
+    J.normal_mode = mc->normal_mode;
+    J.refine_iters = mc->refine_iters;
+    J.shadow = mc->shadow;
+    J.eps_abs = mc->eps_abs;
+    J.eps_rel = mc->eps_rel;
+    J.clamp = mc->step_clamp;
+    J.t_max = mc->t_max;
+    const double ll = norm3(mc->light_dir);
+    for (int k = 0; k < 3; ++k) {
+        J.light[k] = float(mc->light_dir[k] / ll);
+        J.albedo[k] = mc->albedo[k];
+    }
+    J.k_a = mc->k_ambient;
+    J.k_d = mc->k_diffuse;
+    // outputs
+    J.depth = out.depth;
+    J.normal = out.normal;
+    J.colour = out.colour;
+    J.status = out.status;
+    J.counters = out.counters;
+    J.npix = int64_t(cam->width) * cam->height;
+    J.ray_begin = ray_begin;
+    J.ray_count = int64_t(J.tiles_x) * J.tiles_y * frt::kRaysPerTile;
+}
+
+int variant_of(const JobDev& J) {
+    if (J.kind == FRT_JULIA) return frt::kVarJulia;
+    if (J.int_power == 8) return frt::kVarBulb8;
+    return J.int_power > 0 ? frt::kVarBulbInt : frt::kVarBulbReal;
+}
+
+// ----------------------------------------------------- staging and graphs
+struct Staging {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;   // recorded after the last upload from `host`
+    bool pending = false;
+};
+std::mutex g_stage_mu;
+Staging g_stage;
+
+struct GraphEntry {
+    void* workspace;
+    int variant;
+    LaunchCfg cfg;
+    int device;
+    bool any_shadow;
+    hipGraphExec_t exec;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+hipStream_t g_capture_stream = nullptr;
+
+frt_status upload_table(const std::vector<JobDev>& jobs, const WorkspaceHeader& hdr, void* workspace,
+                        hipStream_t stream) {
+    const size_t bytes = sizeof(WorkspaceHeader) + jobs.size() * sizeof(JobDev);
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    hipError_t e;
+    if (g_stage.pending) {
+        e = hipEventSynchronize(g_stage.done);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        g_stage.pending = false;
+    }
+    if (g_stage.bytes < bytes) {
+        if (g_stage.host) (void)hipHostFree(g_stage.host);
+        g_stage.host = nullptr;
+        g_stage.bytes = 0;
+        e = hipHostMalloc(&g_stage.host, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+        g_stage.bytes = bytes;
+    }
+    if (!g_stage.done) {
+        e = hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    std::memcpy(g_stage.host, &hdr, sizeof(hdr));
+    std::memcpy(static_cast<char*>(g_stage.host) + sizeof(hdr), jobs.data(), jobs.size() * sizeof(JobDev));
+    e = hipMemcpyAsync(workspace, g_stage.host, bytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipEventRecord(g_stage.done, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    g_stage.pending = true;
+    return FRT_OK;
+}
+
+frt_status check_workspace(void* workspace, size_t ws_bytes, int32_t n_jobs) {
+    if (!workspace) return fail(FRT_EINVAL, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FRT_EINVAL, "workspace not 256-byte aligned");
+    if (ws_bytes < frt_workspace_bytes(n_jobs)) return fail(FRT_ENOMEM, "workspace too small");
+    return FRT_OK;
+}
+
+}  // namespace
+
+// ======================================================================
+extern "C" {
+
+size_t frt_workspace_bytes(int32_t n_jobs) {
+    if (n_jobs < 1) n_jobs = 1;
+    return size_t(round_up(int64_t(sizeof(WorkspaceHeader)) + int64_t(n_jobs) * int64_t(sizeof(JobDev)), 256));
+}
+
+frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_plane* planes, int32_t n_planes,
+                      const frt_march* march, frt_frame out, void* workspace, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    std::string why;
+    if (!validate(cam, frac, planes, n_planes, march, &out, true, why)) return fail(FRT_EINVAL, why);
+    frt_status s = check_workspace(workspace, ws_bytes, 1);
+    if (s != FRT_OK) return s;
+    JobDev J;
+    pack(cam, frac, planes, n_planes, march, out, 0, J);
+    const int var = variant_of(J);
+    LaunchCfg cfg;
+    if (!make_cfg(frt::trace_kernel_symbol(var, false), var, cfg, why)) return fail(FRT_EHIP, why);
+    hipError_t e = frt::launch_trace(var, false, cfg, nullptr, J, static_cast<WorkspaceHeader*>(workspace),
+                                     J.shadow != 0, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "trace launch");
+    return FRT_OK;
+}
+
+frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace, size_t ws_bytes, int32_t use_graph,
+                            void* stream) {
+    g_last_error.clear();
+    if (!jobs || n_jobs < 1) return fail(FRT_EINVAL, "jobs is null or n_jobs < 1");
+    if (use_graph != 0 && use_graph != 1) return fail(FRT_EINVAL, "use_graph must be 0 or 1");
+    frt_status s = check_workspace(workspace, ws_bytes, n_jobs);
+    if (s != FRT_OK) return s;
+    std::vector<JobDev> table(static_cast<size_t>(n_jobs));
+    int64_t begin = 0;
+    int var = -1;
+    bool any_shadow = false;
+    for (int i = 0; i < n_jobs; ++i) {
+        std::string why;
+        const frt_job& jb = jobs[i];
+        if (!validate(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, &jb.out, true, why))
+            return fail(FRT_EINVAL, "job " + std::to_string(i) + ": " + why);
+        pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, begin, table[size_t(i)]);
+        begin += table[size_t(i)].ray_count;
+        any_shadow = any_shadow || table[size_t(i)].shadow != 0;
+        const int v = variant_of(table[size_t(i)]);
+        var = (var < 0 || var == v) ? v : frt::kVarMixed;
+    }
+    WorkspaceHeader hdr;
+    std::memset(&hdr, 0, sizeof(hdr));
+    hdr.total_rays = static_cast<unsigned long long>(begin);
+    hdr.n_jobs = n_jobs;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    s = upload_table(table, hdr, workspace, st);
+    if (s != FRT_OK) return s;
+    const JobDev* dev_jobs = reinterpret_cast<const JobDev*>(static_cast<char*>(workspace) + sizeof(WorkspaceHeader));
+    std::string why;
+    LaunchCfg cfg;
+    if (!make_cfg(frt::trace_kernel_symbol(var, true), var, cfg, why)) return fail(FRT_EHIP, why);
+    WorkspaceHeader* dhdr = static_cast<WorkspaceHeader*>(workspace);
+    if (!use_graph) {
+        hipError_t e = frt::launch_trace(var, true, cfg, dev_jobs, table[0], dhdr, any_shadow, st);
+        if (e != hipSuccess) return hip_fail(e, "trace launch");
+        return FRT_OK;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    hipGraphExec_t exec = nullptr;
+    for (const GraphEntry& g : g_graphs) {
+        if (g.workspace == workspace && g.variant == var && g.device == dev && g.any_shadow == any_shadow &&
+            g.cfg.grid == cfg.grid && g.cfg.block == cfg.block && g.cfg.chunk == cfg.chunk &&
+            g.cfg.bodies_per_trip == cfg.bodies_per_trip && g.cfg.rare_lanes == cfg.rare_lanes) {
+            exec = g.exec;
+            break;
+        }
+    }
+    hipError_t e;
+    if (!exec) {
+        if (!g_capture_stream) {
+            e = hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        }
+        e = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t le = frt::launch_trace(var, true, cfg, dev_jobs, table[0], dhdr, any_shadow, g_capture_stream);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(g_capture_stream, &graph);
+        if (le != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(le, "trace launch during capture");
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        g_graphs.push_back(GraphEntry{workspace, var, cfg, dev, any_shadow, exec});
+    }
+    e = hipGraphLaunch(exec, st);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return FRT_OK;
+}
+
+frt_status frt_distance(const frt_fractal* frac, const float* points, int64_t n, float* d, int32_t* iters,
+                        void* stream) {
+    g_last_error.clear();
+    if (!frac) return fail(FRT_EINVAL, "null fractal");
+    if (n < 0) return fail(FRT_EINVAL, "n must be >= 0");
+    if (n == 0) return FRT_OK;
+    if (!points || !d) return fail(FRT_EINVAL, "null points or output");
+    frt_camera cam{};
+    cam.eye[2] = 1.0f;
+    cam.up[1] = 1.0f;
+    cam.fov_y_deg = 45.0f;
+    cam.width = cam.height = 1;
+    frt_march mc{};
+    mc.max_steps = 1;
+    mc.eps_abs = 1.0f;
+    mc.step_clamp = 1.0f;
+    mc.t_max = 2.0f;
+    mc.light_dir[1] = 1.0f;
+    std::string why;
+    if (!validate(&cam, frac, nullptr, 0, &mc, nullptr, false, why)) return fail(FRT_EINVAL, why);
+    frt_frame none{};
+    JobDev J;
+    pack(&cam, frac, nullptr, 0, &mc, none, 0, J);
+    frt::OrbitParams P;
+    P.c0 = J.c[0]; P.c1 = J.c[1]; P.c2 = J.c[2]; P.c3 = J.c[3];
+    P.n = J.power;
+    P.nm1_half = 0.5f * (J.power - 1.0f);
+    P.n_rev = J.n_rev;
+    P.ipow = J.int_power;
+    P.kind = J.kind;
+    P.max_iter = J.max_iter;
+    P.bail2 = J.bailout2;
+    hipError_t e = frt::launch_distance(variant_of(J), P, points, n, d, iters, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "distance launch");
+    return FRT_OK;
+}
+
+frt_status frt_math_eval(int32_t func, const float* x, const float* y, float* out, int64_t n, void* stream) {
+    g_last_error.clear();
+    if (func < 0 || func > 7) return fail(FRT_EINVAL, "func must be in [0, 7]");
+    if (n < 0) return fail(FRT_EINVAL, "n must be >= 0");
+    if (n == 0) return FRT_OK;
+    if (!x || !out || (func == 1 && !y)) return fail(FRT_EINVAL, "null input or output");
+    hipError_t e = frt::launch_math(func, x, y, out, n, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "math launch");
+    return FRT_OK;
+}
+
+frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float* const* g_colour,
+                               const float* const* g_depth, const float* const* g_normal, float* grad_c,
+                               float* grad_power, float* grad_plane, void* workspace, size_t ws_bytes,
+                               void* stream) {
+    (void)jobs; (void)n_jobs; (void)g_colour; (void)g_depth; (void)g_normal; (void)grad_c; (void)grad_power;
+    (void)grad_plane; (void)workspace; (void)ws_bytes; (void)stream;
+    g_last_error.clear();
+    return fail(FRT_EUNSUPPORTED, "adjoint not built");
+}
+
+frt_status frt_autotune_set(int32_t kernel_variant, int32_t block, int32_t chunk, int32_t waves_per_simd,
+                            int32_t bodies_per_trip, int32_t rare_lanes) {
+    g_last_error.clear();
+    if (kernel_variant < 0 || kernel_variant >= frt::kNumVariants) return fail(FRT_EINVAL, "unknown kernel_variant");
+    if (block != 64 && block != 128 && block != 256 && block != 512) return fail(FRT_EINVAL, "block must be 64..512");
+    if (chunk < 64 || chunk > 4096 || chunk % 64 != 0) return fail(FRT_EINVAL, "chunk must be a multiple of 64 in [64, 4096]");
+    if (waves_per_simd < 0 || waves_per_simd > 8) return fail(FRT_EINVAL, "waves_per_simd must be in [0, 8]");
+    if (bodies_per_trip < 1 || bodies_per_trip > 64) return fail(FRT_EINVAL, "bodies_per_trip must be in [1, 64]");
+    if (rare_lanes < 1 || rare_lanes > 64) return fail(FRT_EINVAL, "rare_lanes must be in [1, 64]");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tune[kernel_variant] = Tune{block, chunk, waves_per_simd, bodies_per_trip, rare_lanes};
+    return FRT_OK;
+}
+
+frt_status frt_autotune_get(int32_t kernel_variant, int32_t* block, int32_t* chunk, int32_t* waves_per_simd,
+                            int32_t* bodies_per_trip, int32_t* rare_lanes) {
+    g_last_error.clear();
+    if (kernel_variant < 0 || kernel_variant >= frt::kNumVariants) return fail(FRT_EINVAL, "unknown kernel_variant");
+    if (!block || !chunk || !waves_per_simd || !bodies_per_trip || !rare_lanes) {
+        return fail(FRT_EINVAL, "null output pointer");
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    const Tune& t = g_tune[kernel_variant];
+    *block = t.block;
+    *chunk = t.chunk;
+    *waves_per_simd = t.waves_per_simd;
+    *bodies_per_trip = t.bodies_per_trip;
+    *rare_lanes = t.rare_lanes;
+    return FRT_OK;
+}
+
+frt_status frt_graph_reset(void) {
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (GraphEntry& g : g_graphs) (void)hipGraphExecDestroy(g.exec);
+    g_graphs.clear();
+    return FRT_OK;
+}
+
+const char* frt_status_string(frt_status s) {
+    switch (s) {
+        case FRT_OK: return "ok";
+        case FRT_EINVAL: return "invalid argument";
+        case FRT_EHIP: return "HIP runtime error";
+        case FRT_ENOMEM: return "workspace too small";
+        case FRT_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* frt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

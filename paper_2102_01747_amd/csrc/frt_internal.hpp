@@ -1,0 +1,43 @@
+// frt_internal.hpp -- launch interface between the host API and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "frt_job.hpp"
+
+namespace frt {
+
+struct LaunchCfg {
+    int grid;             // workgroups of the march kernels (persistent: fill the chip once)
+    int normal_grid;      // workgroups of the normal kernel (grid-stride)
+    int block;            // threads per workgroup, multiple of 64
+    int chunk;            // rays claimed from the queue per refill
+    int bodies_per_trip;  // orbit bodies a lane advances per loop trip
+    int rare_lanes;       // waiting lanes that trigger shading / refill
+};
+
+// Forward pass: resets the ray queues in the workspace header, then launches
+// the primary march, the normal kernel and (if any_shadow) the shadow march.
+// batch = false reads the job from `job1` (kernel argument); batch = true
+// reads `jobs` (device table) and the ray count from `hdr`.
+hipError_t launch_trace(int variant, bool batch, const LaunchCfg& cfg, const JobDev* jobs, const JobDev& job1,
+                        WorkspaceHeader* hdr, bool any_shadow, hipStream_t stream);
+const void* trace_kernel_symbol(int variant, bool batch);
+
+// Point queries (frt_query.hip).
+struct OrbitParams;
+hipError_t launch_distance(int variant, const OrbitParams& P, const float* pts, long long n, float* d, int* it,
+                           hipStream_t stream);
+hipError_t launch_math(int func, const float* x, const float* y, float* out, long long n, hipStream_t stream);
+
+// Adjoint kernel over the hit pixels of a batch (device job table).
+struct AdjointArgs {
+    const JobDev* jobs;        // device table
+    const AdjointJob* ajobs;   // device table of upstream-gradient pointers
+    float* grad;               // [n_jobs][kGradSlots]
+    int n_jobs;
+};
+hipError_t launch_adjoint(const LaunchCfg& cfg, const AdjointArgs& a, WorkspaceHeader* hdr, hipStream_t stream);
+const void* adjoint_kernel_symbol();
+
+}  // namespace frt

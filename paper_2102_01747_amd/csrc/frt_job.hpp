@@ -1,0 +1,91 @@
+// frt_job.hpp -- device-side job descriptor, built by the host API from the
+// public frt_job (camera basis, bounding radius and unit plane normals are
+// precomputed once per render) and read by the kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace frt {
+
+enum Kind : int32_t { kJulia = 0, kBulb = 1 };
+
+// kernel variants (template argument and autotuner key)
+enum Variant : int32_t {
+    kVarJulia = 0,      // quaternion Julia
+    kVarBulbReal = 1,   // Mandelbulb, real power (trigonometric map)
+    kVarBulbInt = 2,    // Mandelbulb, integer power read at run time
+    kVarMixed = 3,      // several kinds in one batch
+    kVarBulb8 = 4,      // Mandelbulb, power 8 fixed at compile time
+    kNumVariants = 5
+};
+
+// status byte
+enum : uint8_t {
+    kMissBounds = 0,
+    kMissTmax = 1,
+    kHit = 2,
+    kHitCut = 3,
+    kHitExhausted = 4,
+    kFlagShadowed = 8,
+    kFlagUnrefined = 16,
+};
+
+constexpr int kTile = 8;               // rays are issued in 8x8 pixel tiles
+constexpr int kRaysPerTile = kTile * kTile;
+
+struct alignas(16) JobDev {
+    // camera
+    float eye[3];
+    float fwd[3];
+    float right[3];
+    float upv[3];
+    float sx, sy;          // s*W/H and s, s = tan(fov_y/2)
+    float inv_w2, inv_h2;  // 2/W and 2/H
+    int32_t width, height, tiles_x, tiles_y;
+    // fractal
+    int32_t kind, int_power, max_iter, n_planes;
+    float c[4];
+    float power, n_rev, bailout2, radius;   // n_rev = n / (2 pi)
+    // planes (unit normals)
+    float pn[2][3];
+    float pd[2];
+    // march / shading
+    int32_t max_steps, normal_mode, refine_iters, shadow;
+    float eps_abs, eps_rel, clamp, t_max;
+    float light[3];
+    float albedo[3];
+    float k_a, k_d;
+    // outputs (SoA planes of npix)
+    float* depth;
+    float* normal;
+    float* colour;
+    uint8_t* status;
+    uint32_t* counters;
+    int64_t npix;
+    // position in the batch's ray index space (multiples of 64)
+    int64_t ray_begin;
+    int64_t ray_count;
+};
+
+// Gradient slots per job: c0..c3, power, plane 0 (raw n xyz, d), plane 1.
+constexpr int kGradSlots = 13;
+
+// Upstream gradients of one job for the adjoint (device pointers, the last
+// two may be null).
+struct AdjointJob {
+    const float* g_colour;   // [3][P]
+    const float* g_depth;    // [P]
+    const float* g_normal;   // [3][P]
+    float raw_n[2][3];       // raw plane normals (the job holds unit ones)
+};
+
+// Workspace layout: a 256-byte header, then the job table.
+struct alignas(256) WorkspaceHeader {
+    unsigned long long queue[2];    // next unclaimed ray: primary march, shadow march
+    unsigned long long total_rays;
+    int32_t n_jobs;
+    int32_t pad[57];
+};
+static_assert(sizeof(WorkspaceHeader) == 256, "workspace header must be 256 bytes");
+
+}  // namespace frt

@@ -1,0 +1,548 @@
+// frt_trace.hip -- forward sphere-tracing kernels for gfx950.
+//
+// One lane per ray, FP32.  The per-pixel path of the paper (Listings 2-5 and
+// 7) runs as three kernels over the rays of a batch, so that each keeps only
+// the state of its own stage in registers (more resident waves per SIMD, which
+// this latency-bound loop needs):
+//   1. march_kernel<primary>: search interval (bounding sphere and cut
+//      planes), cut-face test, sphere-tracing march of Listing 3 and the
+//      bisection refinement of the hit; writes depth, status and counters
+//      (and the plane normal of cut-face hits, and the miss encoding);
+//   2. normal_kernel: normal taps of Eq. 5 / Listing 5 around each refined
+//      hit, the normal, and Lambert shading assuming the point is lit;
+//   3. march_kernel<shadow>: one shadow ray toward the light from every lit
+//      hit; on a hit the pixel is marked shadowed and keeps only ambient light.
+// The two march kernels are persistent: each wave runs one loop in which every
+// busy lane advances its orbit by up to `bodies_per_trip` bodies (Eq. 3-4), so
+// a lane whose orbit escapes early does not wait for the slowest lane; lanes
+// whose estimate is done take their march / refinement step in place and
+// start the next sample; and when `rare_lanes` lanes wait (or none is busy)
+// finished rays are written and idle lanes refill from a global ray queue --
+// one atomic claims `chunk` ray indices, handed out by ballot + mbcnt.  A wave
+// leaves its loop when the ballot of busy lanes is empty and the queue is
+// drained.  One launch of each kernel serves all renders of a batch.
+#include <hip/hip_runtime.h>
+
+#include "frt_fractal.hpp"
+#include "frt_internal.hpp"
+#include "frt_job.hpp"
+
+namespace frt {
+
+// Refinement stops once the root bracket is narrower than eps(t) / 32.
+constexpr float kRefineTol = 1.0f / 32.0f;
+
+template <int VAR> struct OrbitOf;
+template <> struct OrbitOf<kVarJulia> { using T = JuliaOrbit; };
+template <> struct OrbitOf<kVarBulbReal> { using T = BulbOrbit<0>; };
+template <> struct OrbitOf<kVarBulbInt> { using T = BulbOrbit<-1>; };
+template <> struct OrbitOf<kVarBulb8> { using T = BulbOrbit<8>; };
+template <> struct OrbitOf<kVarMixed> { using T = MixedOrbit; };
+
+__device__ __forceinline__ OrbitParams orbit_params(const JobDev& J) {
+    OrbitParams p;
+    p.c0 = J.c[0];
+    p.c1 = J.c[1];
+    p.c2 = J.c[2];
+    p.c3 = J.c[3];
+    p.n = J.power;
+    p.nm1_half = 0.5f * (J.power - 1.0f);
+    p.n_rev = J.n_rev;
+    p.ipow = J.int_power;
+    p.kind = J.kind;
+    p.max_iter = J.max_iter;
+    p.bail2 = J.bailout2;
+    return p;
+}
+
+// Search interval of a ray (text around Listing 3): [tmin, t_max] cut by the
+// bounding sphere and the kept half-spaces.  Returns false when empty;
+// `entry` is the plane whose crossing sets the start strictly after every
+// other lower bound (-1 if none).
+__device__ __forceinline__ bool ray_interval(const JobDev& J, float ox, float oy, float oz, float dx, float dy,
+                                             float dz, float tmin, float& lo, float& hi, int& entry) {
+    const float b = fmaf(ox, dx, fmaf(oy, dy, oz * dz));
+    const float cc = fmaf(ox, ox, fmaf(oy, oy, oz * oz)) - J.radius * J.radius;
+    const float disc = fmaf(b, b, -cc);
+    if (disc < 0.0f) return false;
+    const float sq = sqrtf(disc);
+    lo = fmaxf(tmin, -b - sq);
+    hi = fminf(J.t_max, -b + sq);
+    entry = -1;
+    for (int k = 0; k < J.n_planes; ++k) {
+        const float denom = fmaf(J.pn[k][0], dx, fmaf(J.pn[k][1], dy, J.pn[k][2] * dz));
+        const float num = J.pd[k] - fmaf(J.pn[k][0], ox, fmaf(J.pn[k][1], oy, J.pn[k][2] * oz));
+        if (denom == 0.0f) {
+            if (num < 0.0f) return false;
+        } else if (denom > 0.0f) {
+            hi = fminf(hi, num / denom);
+        } else {
+            const float tk = num / denom;
+            if (tk > lo) {
+                lo = tk;
+                entry = k;
+            }
+        }
+    }
+    return lo <= hi;
+}
+
+// Primary ray through pixel (px, py): pinhole, pixel centre, row 0 at the top.
+__device__ __forceinline__ void primary_dir(const JobDev& J, int px, int py, float& dx, float& dy, float& dz) {
+    const float u = fmaf(px + 0.5f, J.inv_w2, -1.0f) * J.sx;
+    const float v = fmaf(-(py + 0.5f), J.inv_h2, 1.0f) * J.sy;
+    const float rx = fmaf(u, J.right[0], fmaf(v, J.upv[0], J.fwd[0]));
+    const float ry = fmaf(u, J.right[1], fmaf(v, J.upv[1], J.fwd[1]));
+    const float rz = fmaf(u, J.right[2], fmaf(v, J.upv[2], J.fwd[2]));
+    const float inv = rsqrtf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+    dx = rx * inv;
+    dy = ry * inv;
+    dz = rz * inv;
+}
+
+__device__ __forceinline__ unsigned long long bcast_first(unsigned long long v) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
+    return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned lane_rank(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<unsigned>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(mask), 0u));
+}
+
+template <bool BATCH>
+__device__ __forceinline__ const JobDev& job_ref(const JobDev* __restrict__ jobs, const JobDev& job1, int j) {
+    if constexpr (BATCH) return jobs[j]; else return job1;
+}
+
+// Map a ray index of the batch to (job, pixel); false for the padding lanes
+// of edge tiles.
+template <bool BATCH>
+__device__ __forceinline__ bool ray_pixel(const JobDev* __restrict__ jobs, const JobDev& job1, int n_jobs,
+                                          long long g, int& j, int& px, int& py) {
+    j = 0;
+    if constexpr (BATCH) {
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].ray_begin <= g) lo = mid; else hi = mid - 1;
+        }
+        j = lo;
+    }
+    const JobDev& J = job_ref<BATCH>(jobs, job1, j);
+    const long long r = g - J.ray_begin;
+    const int tile = static_cast<int>(r >> 6), wl = static_cast<int>(r & 63);
+    const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
+    px = tx * kTile + (wl & (kTile - 1));
+    py = ty * kTile + (wl >> 3);
+    return px < J.width && py < J.height;
+}
+
+enum MarchPhase : int { kIdle = 0, kCut = 1, kMarch = 2, kRefine = 3, kDone = 4 };
+
+// ---------------------------------------------------------------------------
+// Persistent march kernel.  SHADOW = false: primary rays (interval, cut face,
+// march, refinement).  SHADOW = true: the shadow ray of every lit hit, from
+// p* + 4 eps(t*) N toward the light with threshold eps(t*) (the hit is read
+// back from depth / normal / status written by the earlier kernels).
+// ---------------------------------------------------------------------------
+template <int VAR, bool BATCH, bool SHADOW>
+__global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
+                                                    WorkspaceHeader* __restrict__ hdr, int chunk,
+                                                    int bodies_per_trip, int rare_lanes) {
+    using Orbit = typename OrbitOf<VAR>::T;
+    unsigned long long* queue = &hdr->queue[SHADOW ? 1 : 0];
+    int n_jobs = 1;
+    unsigned long long total_rays = static_cast<unsigned long long>(job1.ray_count);
+    if constexpr (BATCH) {
+        n_jobs = hdr->n_jobs;
+        total_rays = hdr->total_rays;
+    }
+    unsigned long long q_next = 0, q_end = 0;   // wave-uniform queue window
+    bool drained = false;
+
+    int phase = kIdle;
+    int jb = 0, pix = 0, entry = -1, status = 0, steps = 0, rk = 0, hit_it = 0;
+    unsigned evals = 0, bodies = 0;
+    float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 1.f;
+    float t = 0.f, t1 = 0.f, lt = 0.f, lh = 0.f, gb = 0.f, ea = 0.f, er = 0.f;
+    OrbitParams P = orbit_params(job1);
+    Orbit orb;
+    if constexpr (VAR == kVarMixed) orb.set_kind(P);
+
+    for (;;) {
+        // ------------------------------------------ finished rays + refill
+        const unsigned long long m_busy = __ballot(phase == kCut || phase == kMarch || phase == kRefine);
+        const unsigned long long m_done = __ballot(phase == kDone);
+        if (m_busy == 0ull && m_done == 0ull && drained) break;
+        const int waiting = __popcll(m_done) + (drained ? 0 : __popcll(__ballot(phase == kIdle)));
+        if (m_busy == 0ull || waiting >= rare_lanes) {
+            if (phase == kDone) {
+                const JobDev& J = job_ref<BATCH>(jobs, job1, jb);
+                const long long NP = J.npix;
+                if constexpr (!SHADOW) {
+                    const int cls = status & 7;
+                    if (cls == kMissBounds || cls == kMissTmax) {
+                        J.depth[pix] = -1.0f;
+                        J.normal[pix] = 0.0f;
+                        J.normal[NP + pix] = 0.0f;
+                        J.normal[2 * NP + pix] = 0.0f;
+                        J.colour[pix] = 0.0f;
+                        J.colour[NP + pix] = 0.0f;
+                        J.colour[2 * NP + pix] = 0.0f;
+                    } else {
+                        J.depth[pix] = t;
+                        if (cls == kHitCut) {
+                            J.normal[pix] = J.pn[entry][0];
+                            J.normal[NP + pix] = J.pn[entry][1];
+                            J.normal[2 * NP + pix] = J.pn[entry][2];
+                        }
+                    }
+                    J.status[pix] = static_cast<uint8_t>(status);
+                    if (J.counters) {
+                        J.counters[pix] = static_cast<unsigned>(steps);
+                        J.counters[NP + pix] = evals;
+                        J.counters[2 * NP + pix] = bodies;
+                        J.counters[3 * NP + pix] = static_cast<unsigned>(hit_it);
+                    }
+                } else {
+                    if (status & kFlagShadowed) {
+                        J.status[pix] = static_cast<uint8_t>(J.status[pix] | kFlagShadowed);
+                        J.colour[pix] = J.albedo[0] * J.k_a;
+                        J.colour[NP + pix] = J.albedo[1] * J.k_a;
+                        J.colour[2 * NP + pix] = J.albedo[2] * J.k_a;
+                    }
+                    if (J.counters) {
+                        J.counters[NP + pix] += evals;
+                        J.counters[2 * NP + pix] += bodies;
+                    }
+                }
+                phase = kIdle;
+            }
+
+            unsigned long long idle = __ballot(phase == kIdle);
+            while (idle != 0ull && !drained) {
+                if (q_next >= q_end) {
+                    unsigned long long base = 0;
+                    if (__lane_id() == 0) base = atomicAdd(queue, static_cast<unsigned long long>(chunk));
+                    base = bcast_first(base);
+                    if (base >= total_rays) {
+                        drained = true;
+                        break;
+                    }
+                    q_next = base;
+                    q_end = min(base + static_cast<unsigned long long>(chunk), total_rays);
+                }
+                const unsigned rank = lane_rank(idle);
+                const unsigned long long avail = q_end - q_next;
+                int j, px, py;
+                if (phase == kIdle && rank < avail &&
+                    ray_pixel<BATCH>(jobs, job1, n_jobs, static_cast<long long>(q_next + rank), j, px, py)) {
+                    const JobDev& J = job_ref<BATCH>(jobs, job1, j);
+                    const int p = py * J.width + px;
+                    float lo, hi;
+                    bool go = false;
+                    if constexpr (!SHADOW) {
+                        primary_dir(J, px, py, dx, dy, dz);
+                        ox = J.eye[0];
+                        oy = J.eye[1];
+                        oz = J.eye[2];
+                        ea = J.eps_abs;
+                        er = J.eps_rel;
+                        status = 0;
+                        go = ray_interval(J, ox, oy, oz, dx, dy, dz, J.eps_abs, lo, hi, entry);
+                        if (!go) {
+                            // no interval: written as a miss right away
+                            const long long NP = J.npix;
+                            J.depth[p] = -1.0f;
+                            J.normal[p] = 0.0f;
+                            J.normal[NP + p] = 0.0f;
+                            J.normal[2 * NP + p] = 0.0f;
+                            J.colour[p] = 0.0f;
+                            J.colour[NP + p] = 0.0f;
+                            J.colour[2 * NP + p] = 0.0f;
+                            J.status[p] = kMissBounds;
+                            if (J.counters) {
+                                J.counters[p] = 0u;
+                                J.counters[NP + p] = 0u;
+                                J.counters[2 * NP + p] = 0u;
+                                J.counters[3 * NP + p] = 0u;
+                            }
+                        }
+                    } else if (J.shadow && (J.status[p] & 7) >= kHit) {
+                        const long long NP = J.npix;
+                        const float nx = J.normal[p], ny = J.normal[NP + p], nz = J.normal[2 * NP + p];
+                        const float ndl = fmaf(nx, J.light[0], fmaf(ny, J.light[1], nz * J.light[2]));
+                        if (ndl > 0.0f) {
+                            float pdx, pdy, pdz;
+                            primary_dir(J, px, py, pdx, pdy, pdz);
+                            const float ts = J.depth[p];
+                            const float eps = fmaf(J.eps_rel, ts, J.eps_abs);
+                            const float off = 4.0f * eps;
+                            ox = fmaf(off, nx, fmaf(ts, pdx, J.eye[0]));
+                            oy = fmaf(off, ny, fmaf(ts, pdy, J.eye[1]));
+                            oz = fmaf(off, nz, fmaf(ts, pdz, J.eye[2]));
+                            dx = J.light[0];
+                            dy = J.light[1];
+                            dz = J.light[2];
+                            ea = eps;
+                            er = 0.0f;
+                            status = 0;
+                            go = ray_interval(J, ox, oy, oz, dx, dy, dz, eps, lo, hi, entry);
+                        }
+                    }
+                    if (go) {
+                        jb = j;
+                        pix = p;
+                        if constexpr (BATCH) {
+                            P = orbit_params(J);
+                            if constexpr (VAR == kVarMixed) orb.set_kind(P);
+                        }
+                        t = lo;
+                        t1 = hi;
+                        steps = 0;
+                        hit_it = 0;
+                        evals = 0;
+                        bodies = 0;
+                        phase = entry >= 0 ? kCut : kMarch;
+                        orb.init(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz));
+                    }
+                }
+                q_next += min(static_cast<unsigned long long>(__popcll(idle)), avail);
+                idle = __ballot(phase == kIdle);
+            }
+        }
+
+        // -------------------------------------------------- orbit bodies
+        if (phase == kCut || phase == kMarch || phase == kRefine) {
+            for (int b = 0; b < bodies_per_trip && !orb.done(P); ++b) orb.body(P);
+            if (orb.done(P)) {
+                const JobDev& J = job_ref<BATCH>(jobs, job1, jb);
+                const DEResult de = orb.result();
+                evals += 1u;
+                bodies += static_cast<unsigned>(de.bodies);
+                const float d = de.d;
+                if (phase == kCut) {
+                    // cut face: the entry point is inside when its orbit does
+                    // not escape or the estimate is below eps
+                    if (de.it == P.max_iter || d < fmaf(er, t, ea)) {
+                        status = SHADOW ? kFlagShadowed : kHitCut;
+                        if (!SHADOW) hit_it = de.it;
+                        phase = kDone;
+                    } else {
+                        phase = kMarch;
+                    }
+                }
+                if (phase == kMarch) {   // Listing 3
+                    ++steps;
+                    if (!SHADOW) hit_it = de.it;
+                    if (d < fmaf(er, t, ea)) {
+                        if constexpr (SHADOW) {
+                            status = kFlagShadowed;
+                            phase = kDone;
+                        } else if (steps > 1) {
+                            // refine the root of g = d - eps on the bracket
+                            // [lt, t1] of the last two samples, g(lt) >= 0 > g(t1)
+                            status = kHit;
+                            lh -= fmaf(er, lt, ea);
+                            gb = d - fmaf(er, t, ea);
+                            t1 = t;
+                            rk = 0;
+                            if (J.refine_iters > 0 && t1 - lt > kRefineTol * fmaf(er, t1, ea)) {
+                                phase = kRefine;
+                                t = 0.5f * (lt + t1);
+                            } else {
+                                t = fmaf(-gb, (t1 - lt) / (gb - lh), t1);   // secant on the bracket
+                                phase = kDone;
+                            }
+                        } else {
+                            status = kHit | kFlagUnrefined;
+                            phase = kDone;
+                        }
+                    } else {
+                        lt = t;
+                        lh = d;
+                        t += fminf(d, J.clamp);
+                        if (t > t1) {
+                            status = SHADOW ? 0 : kMissTmax;
+                            phase = kDone;
+                        } else if (steps >= J.max_steps) {
+                            status = SHADOW ? kFlagShadowed : (kHitExhausted | kFlagUnrefined);
+                            phase = kDone;
+                        }
+                    }
+                } else if (phase == kRefine) {
+                    // bisection step on [lt, t1]; t is the midpoint just evaluated
+                    const float fx = d - fmaf(er, t, ea);
+                    if (fx < 0.0f) { t1 = t; gb = fx; } else { lt = t; lh = fx; }
+                    ++rk;
+                    if (rk >= J.refine_iters || t1 - lt <= kRefineTol * fmaf(er, t1, ea)) {
+                        t = fmaf(-gb, (t1 - lt) / (gb - lh), t1);   // secant on the final bracket
+                        phase = kDone;
+                    } else {
+                        t = 0.5f * (lt + t1);
+                    }
+                }
+                if (phase == kCut || phase == kMarch || phase == kRefine)
+                    orb.init(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Normal taps (Eq. 5 / Listing 5) and Lambert shading of every hit, one lane
+// per ray of the batch.  Tetrahedral: h = 0.5773 eps(t*), N ~ sum nu_i d(p +
+// h nu_i); central: h = eps(t*), N_k ~ d(p + h e_k) - d(p - h e_k).  A zero
+// gradient falls back to -dir.  Colour assumes the point is lit; the shadow
+// kernel darkens shadowed pixels.
+// ---------------------------------------------------------------------------
+template <int VAR, bool BATCH>
+__global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
+                                                     WorkspaceHeader* __restrict__ hdr) {
+    using Orbit = typename OrbitOf<VAR>::T;
+    int n_jobs = 1;
+    unsigned long long total_rays = static_cast<unsigned long long>(job1.ray_count);
+    if constexpr (BATCH) {
+        n_jobs = hdr->n_jobs;
+        total_rays = hdr->total_rays;
+    }
+    const unsigned long long stride = static_cast<unsigned long long>(gridDim.x) * blockDim.x;
+    for (unsigned long long g = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+         g < total_rays; g += stride) {
+        int j, px, py;
+        if (!ray_pixel<BATCH>(jobs, job1, n_jobs, static_cast<long long>(g), j, px, py)) continue;
+        const JobDev& J = job_ref<BATCH>(jobs, job1, j);
+        const int p = py * J.width + px;
+        const int cls = J.status[p] & 7;
+        if (cls < kHit) continue;
+        const long long NP = J.npix;
+        float nx, ny, nz;
+        unsigned evals = 0, bodies = 0;
+        if (cls == kHitCut) {
+            nx = J.normal[p];
+            ny = J.normal[NP + p];
+            nz = J.normal[2 * NP + p];
+        } else {
+            const OrbitParams P = orbit_params(J);
+            Orbit orb;
+            if constexpr (VAR == kVarMixed) orb.set_kind(P);
+            float dx, dy, dz;
+            primary_dir(J, px, py, dx, dy, dz);
+            const float ts = J.depth[p];
+            const float eps = fmaf(J.eps_rel, ts, J.eps_abs);
+            const float sx = fmaf(ts, dx, J.eye[0]), sy = fmaf(ts, dy, J.eye[1]), sz = fmaf(ts, dz, J.eye[2]);
+            float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+            if (J.normal_mode == 0) {
+                const float h = 0.5773f * eps;
+                for (int k = 0; k < 4; ++k) {
+                    const float vx = (k == 0 || k == 3) ? 1.0f : -1.0f;
+                    const float vy = (k >= 2) ? 1.0f : -1.0f;
+                    const float vz = (k == 1 || k == 3) ? 1.0f : -1.0f;
+                    const DEResult r = de_once(orb, P, fmaf(h, vx, sx), fmaf(h, vy, sy), fmaf(h, vz, sz));
+                    gx = fmaf(vx, r.d, gx);
+                    gy = fmaf(vy, r.d, gy);
+                    gz = fmaf(vz, r.d, gz);
+                    bodies += static_cast<unsigned>(r.bodies);
+                }
+                evals = 4;
+            } else {
+                const float h = eps;
+                for (int k = 0; k < 6; ++k) {
+                    const float sg = (k & 1) ? -h : h;
+                    const int ax = k >> 1;
+                    const DEResult r = de_once(orb, P, ax == 0 ? sx + sg : sx, ax == 1 ? sy + sg : sy,
+                                               ax == 2 ? sz + sg : sz);
+                    const float sd = (k & 1) ? -r.d : r.d;
+                    if (ax == 0) gx += sd; else if (ax == 1) gy += sd; else gz += sd;
+                    bodies += static_cast<unsigned>(r.bodies);
+                }
+                evals = 6;
+            }
+            const float gl2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+            if (gl2 > 0.0f) {
+                const float inv = rsqrtf(gl2);
+                nx = gx * inv;
+                ny = gy * inv;
+                nz = gz * inv;
+            } else {
+                nx = -dx;
+                ny = -dy;
+                nz = -dz;
+            }
+            J.normal[p] = nx;
+            J.normal[NP + p] = ny;
+            J.normal[2 * NP + p] = nz;
+        }
+        const float ndl = fmaf(nx, J.light[0], fmaf(ny, J.light[1], nz * J.light[2]));
+        const float lam = fmaf(J.k_d, fmaxf(ndl, 0.0f), J.k_a);
+        J.colour[p] = J.albedo[0] * lam;
+        J.colour[NP + p] = J.albedo[1] * lam;
+        J.colour[2 * NP + p] = J.albedo[2] * lam;
+        if (J.counters && evals) {
+            J.counters[NP + p] += evals;
+            J.counters[2 * NP + p] += bodies;
+        }
+    }
+}
+
+__global__ void reset_queue_kernel(WorkspaceHeader* hdr) {
+    if (threadIdx.x < 2) hdr->queue[threadIdx.x] = 0ull;
+}
+
+template <int VAR, bool BATCH>
+static hipError_t launch_var(const LaunchCfg& cfg, const JobDev* jobs, const JobDev& job1, WorkspaceHeader* hdr,
+                             bool any_shadow, hipStream_t stream) {
+    hipLaunchKernelGGL((march_kernel<VAR, BATCH, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, jobs, job1,
+                       hdr, cfg.chunk, cfg.bodies_per_trip, cfg.rare_lanes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((normal_kernel<VAR, BATCH>), dim3(cfg.normal_grid), dim3(256), 0, stream, jobs, job1, hdr);
+    e = hipGetLastError();
+    if (e != hipSuccess || !any_shadow) return e;
+    hipLaunchKernelGGL((march_kernel<VAR, BATCH, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, jobs, job1,
+                       hdr, cfg.chunk, cfg.bodies_per_trip, cfg.rare_lanes);
+    return hipGetLastError();
+}
+
+template <int VAR, bool BATCH>
+static const void* kernel_ptr() {
+    return reinterpret_cast<const void*>(&march_kernel<VAR, BATCH, false>);
+}
+
+const void* trace_kernel_symbol(int variant, bool batch) {
+    switch (variant) {
+        case kVarJulia: return batch ? kernel_ptr<kVarJulia, true>() : kernel_ptr<kVarJulia, false>();
+        case kVarBulbReal: return batch ? kernel_ptr<kVarBulbReal, true>() : kernel_ptr<kVarBulbReal, false>();
+        case kVarBulbInt: return batch ? kernel_ptr<kVarBulbInt, true>() : kernel_ptr<kVarBulbInt, false>();
+        case kVarBulb8: return batch ? kernel_ptr<kVarBulb8, true>() : kernel_ptr<kVarBulb8, false>();
+        default: return batch ? kernel_ptr<kVarMixed, true>() : kernel_ptr<kVarMixed, false>();
+    }
+}
+
+hipError_t launch_trace(int variant, bool batch, const LaunchCfg& cfg, const JobDev* jobs, const JobDev& job1,
+                        WorkspaceHeader* hdr, bool any_shadow, hipStream_t stream) {
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, stream, hdr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (variant) {
+        case kVarJulia:
+            return batch ? launch_var<kVarJulia, true>(cfg, jobs, job1, hdr, any_shadow, stream)
+                         : launch_var<kVarJulia, false>(cfg, jobs, job1, hdr, any_shadow, stream);
+        case kVarBulbReal:
+            return batch ? launch_var<kVarBulbReal, true>(cfg, jobs, job1, hdr, any_shadow, stream)
+                         : launch_var<kVarBulbReal, false>(cfg, jobs, job1, hdr, any_shadow, stream);
+        case kVarBulbInt:
+            return batch ? launch_var<kVarBulbInt, true>(cfg, jobs, job1, hdr, any_shadow, stream)
+                         : launch_var<kVarBulbInt, false>(cfg, jobs, job1, hdr, any_shadow, stream);
+        case kVarBulb8:
+            return batch ? launch_var<kVarBulb8, true>(cfg, jobs, job1, hdr, any_shadow, stream)
+                         : launch_var<kVarBulb8, false>(cfg, jobs, job1, hdr, any_shadow, stream);
+        default:
+            return batch ? launch_var<kVarMixed, true>(cfg, jobs, job1, hdr, any_shadow, stream)
+                         : launch_var<kVarMixed, false>(cfg, jobs, job1, hdr, any_shadow, stream);
+    }
+}
+
+}  // namespace frt

@@ -1,0 +1,168 @@
+"""GPU-vs-oracle comparison rules shared by the GPU tests and the benchmark.
+
+Hit/miss agreement is measured over every compared pixel.  Depth, class and
+normal are compared where both sides hit and the pixel is not in the
+boundary set B, the pixels whose outcome is decided by FP32-vs-FP64 rounding
+rather than by the method:
+  - an 8-neighbour has a different oracle hit/miss or cut-face outcome;
+  - either side ran out of steps, or the oracle's root bracket closed on a
+    jump of the estimate (no smooth root there);
+  - the escape count at the last march sample differs between the sides;
+  - the ray grazes the surface (|N . dir| < 0.05).
+Depth tolerance: 2 eps(t*).  Normal tolerance: 1e-3 rad, measured against
+the oracle's normal evaluated at the GPU's own hit point (which separates
+the normal estimate from the depth error); the angle to the oracle's normal
+at its own hit point is reported as well.
+
+Normals are compared on a further restricted set: a pixel's normal is
+ill-conditioned at float32 resolution when
+  - a normal tap's orbit does not escape (the estimate there follows the
+    unconverged, chaotic orbit), or comes within 1e-4 (relative) of the
+    bailout (its escape count, where the estimate jumps, is decided by
+    rounding); or
+  - the FP64 normal moves by more than 2e-4 rad when the power z^p of every
+    orbit body is perturbed by a random relative 2 p 2^-24 (the rounding
+    budget of a p-th power in float32) over four seeds.  Near the set z^p + c
+    cancels, so that rounding is amplified; float32 emulation of the kernel
+    arithmetic reproduces the GPU's deviations at such pixels.
+"""
+import numpy as np
+
+CLS_MASK = 7
+HIT_CLASSES = (2, 3, 4)
+
+
+def to_numpy(frame):
+    out = {}
+    for k, v in frame.items():
+        out[k] = v.detach().cpu().numpy() if hasattr(v, "detach") else np.asarray(v)
+    return out
+
+
+def angle(a, b):
+    """Angle between rows of a and b, each normalised in float64 first; the
+    atan2 form stays accurate for nearly parallel vectors, where arccos of a
+    dot product of float32-normalised vectors is not."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    a = a / np.linalg.norm(a, axis=-1, keepdims=True)
+    b = b / np.linalg.norm(b, axis=-1, keepdims=True)
+    return np.arctan2(np.linalg.norm(np.cross(a, b), axis=-1), np.einsum("...i,...i->...", a, b))
+
+
+def neighbour_flags(status_img):
+    """Per pixel: does any 8-neighbour differ in hit/miss or in cut-face-ness?"""
+    cls = status_img & CLS_MASK
+    hit = cls >= 2
+    cut = cls == 3
+    H, W = cls.shape
+    diff = np.zeros((H, W), bool)
+    hp = np.pad(hit, 1, mode="edge")
+    cp = np.pad(cut, 1, mode="edge")
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dy == 0 and dx == 0:
+                continue
+            sh = hp[1 + dy:1 + dy + H, 1 + dx:1 + dx + W]
+            sc = cp[1 + dy:1 + dy + H, 1 + dx:1 + dx + W]
+            diff |= (sh != hit) | (sc != cut)
+    return diff
+
+
+def neighbourhood_pixels(pixels, width, height):
+    """The 3x3 neighbourhoods (clamped) of sampled pixels, shape [n, 9]."""
+    py, px = np.divmod(np.asarray(pixels, np.int64), width)
+    out = []
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            out.append(np.clip(py + dy, 0, height - 1) * width + np.clip(px + dx, 0, width - 1))
+    return np.stack(out, 1)
+
+
+def normal_ill_conditioned(orc, fr, mc, pts, dirs, eps, seeds=4, tol=2e-4, margin=1e-4):
+    """Per point: is the FP64 normal estimate ill-conditioned at float32
+    resolution (see the module docstring)?"""
+    if len(pts) == 0:
+        return np.zeros(0, bool)
+    tp = orc.tap_points(pts, eps, mc["normal_mode"])
+    mg, esc = orc.escape_margin(fr, tp.reshape(-1, 3))
+    ntap = tp.shape[1]
+    ill = ~esc.reshape(-1, ntap).all(1) | (mg.reshape(-1, ntap).min(1) < margin)
+    p = fr["power"] if fr["kind"] == "bulb" else 2.0
+    ref = orc.normal_at(fr, pts, dirs, eps, mc["normal_mode"])
+    for s in range(seeds):
+        pert = orc.normal_perturbed(fr, pts, dirs, eps, mc["normal_mode"], 2.0 * p * 2.0 ** -24, 1000 + s)
+        ill |= angle(pert, ref) > tol
+    return ill
+
+
+def compare(orc, job, g, o, neigh_diff, pixels=None):
+    """g: GPU frame (numpy, restricted to `pixels` if given); o: oracle render
+    of the same pixels; neigh_diff: neighbour flags of those pixels."""
+    cam, mc, fr = job["camera"], job["march"], job["fractal"]
+    n = o["depth"].size
+    if pixels is None:
+        pixels = np.arange(n)
+    gs, os_ = g["status"].astype(np.int64), o["status"].astype(np.int64)
+    gc, oc = gs & CLS_MASK, os_ & CLS_MASK
+    ghit, ohit = gc >= 2, oc >= 2
+    stats = {"pixels": int(n), "hit_agree": float(np.mean(ghit == ohit)), "gpu_hits": int(ghit.sum()),
+             "oracle_hits": int(ohit.sum())}
+    orig, dirs = orc.camera_rays(cam, pixels)
+    B = neigh_diff.copy()
+    B |= (gc == 4) | (oc == 4) | ((os_ & 32) != 0)
+    if "counters" in g:
+        B |= (g["counters"][3].astype(np.int64) != o["hit_iters"])
+    on = o["normal"].T
+    B |= ohit & (np.abs(np.einsum("ij,ij->i", on, dirs)) < 0.05)
+    both = ghit & ohit & ~B
+    stats["boundary_frac"] = float(B.mean())
+    stats["compared"] = int(both.sum())
+    stats["class_agree"] = float(np.mean(gc[both] == oc[both])) if both.any() else 1.0
+    ts = o["depth"][both]
+    eps = mc["eps_abs"] + mc["eps_rel"] * ts
+    derr = np.abs(g["depth"][both] - ts)
+    stats["depth_ok"] = float(np.mean(derr <= 2 * eps)) if both.any() else 1.0
+    stats["depth_err_max_over_eps"] = float(np.max(derr / eps)) if both.any() else 0.0
+    # normal: oracle normal at the GPU's hit point (cut faces: the plane normal on both sides)
+    gn = g["normal"].T[both]
+    idx = np.nonzero(both)[0]
+    p_g = orig[idx] + g["depth"][idx, None].astype(np.float64) * dirs[idx]
+    eps_g = mc["eps_abs"] + mc["eps_rel"] * g["depth"][idx].astype(np.float64)
+    n_at = orc.normal_at(fr, p_g, dirs[idx], eps_g, mc["normal_mode"])
+    cut = gc[idx] == 3
+    n_at[cut] = on[idx][cut]
+    ang = angle(gn, n_at)
+    ang_own = angle(gn, on[idx])
+    ill = normal_ill_conditioned(orc, fr, mc, p_g, dirs[idx], eps_g)
+    ill[cut] = False
+    wc = ~ill
+    stats["normal_boundary_frac"] = float(ill.mean()) if both.any() else 0.0
+    stats["normal_ok"] = float(np.mean(ang[wc] <= 1e-3)) if wc.any() else 1.0
+    stats["normal_ang_p99"] = float(np.percentile(ang[wc], 99)) if wc.any() else 0.0
+    stats["normal_ang_max"] = float(np.max(ang[wc])) if wc.any() else 0.0
+    stats["normal_ok_vs_oracle_point"] = float(np.mean(ang_own[wc] <= 1e-3)) if wc.any() else 1.0
+    # colour where the shadow outcome agrees and the normal is well conditioned
+    # (error bounded by k_d |dN|)
+    keep = np.zeros(n, bool)
+    keep[idx[wc]] = True
+    same_v = keep & ((gs & 8) == (os_ & 8))
+    cerr = np.abs(g["colour"][:, same_v] - o["colour"][:, same_v]).max(0) if same_v.any() else np.zeros(0)
+    stats["colour_ok"] = float(np.mean(cerr <= 2e-3)) if same_v.any() else 1.0
+    stats["colour_err_max"] = float(cerr.max()) if same_v.any() else 0.0
+    stats["shadow_agree"] = float(np.mean((gs[both] & 8) == (os_[both] & 8))) if both.any() else 1.0
+    # misses carry the miss encoding
+    gm = ~ghit
+    stats["miss_encoding_ok"] = bool(np.all(g["depth"][gm] == -1.0) and np.all(g["normal"][:, gm] == 0.0)
+                                     and np.all(g["colour"][:, gm] == 0.0))
+    return stats
+
+
+def assert_parity(stats, hit_agree=0.999, depth_ok=1.0, normal_ok=0.999, class_agree=1.0):
+    msg = str(stats)
+    assert stats["hit_agree"] >= hit_agree, msg
+    assert stats["depth_ok"] >= depth_ok, msg
+    assert stats["class_agree"] >= class_agree, msg
+    assert stats["normal_ok"] >= normal_ok, msg
+    assert stats["colour_ok"] >= normal_ok, msg
+    assert stats["miss_encoding_ok"], msg

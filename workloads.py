@@ -45,7 +45,7 @@ def orbit_eye(radius, azimuth, elevation):
 
 
 def march(max_steps, eps_abs=0.0, eps_rel=0.0, normal_mode="tetra", shadow=False, step_clamp=0.2,
-          t_max=7000.0, refine_iters=3):
+          t_max=7000.0, refine_iters=12):
     return {"max_steps": int(max_steps), "eps_abs": f32(eps_abs), "eps_rel": f32(eps_rel),
             "step_clamp": f32(step_clamp), "t_max": f32(t_max), "normal_mode": normal_mode,
             "refine_iters": int(refine_iters), "shadow": bool(shadow), "light_dir": list(LIGHT_DIR),
