@@ -3,13 +3,17 @@
 Workload (one step): the eight 1920x1080 views of the power-8 Mandelbulb
 (eye at radius 2.5, seeded azimuth/elevation, 10 orbit iterations, r > 2,
 512 steps, eps = 5e-4 t, central-difference normals, one shadow ray per lit
-hit), rendered in one persistent batch launch.  Inputs (camera and fractal
+hit), rendered in one batch (primary-march, normal and shadow-march kernels,
+each one launch over all eight views).  Inputs (camera and fractal
 parameters) and output planes are resident in HBM before timing starts.
 
-Prints one JSON line with the throughput, the roofline of the trace kernel
-(algorithmic FP32 FLOP per launch over its HIP-event-measured duration, against
-the 157.3 TFLOP/s FP32 vector peak) and the FP64 CPU oracle timed on a
-bounded pixel sample of the same workload on the host cores.
+Before timing, the launch configuration is autotuned on this workload
+(untimed; --no-tune keeps the library defaults).  Prints one JSON line with
+the throughput, the roofline of the dominant kernel (algorithmic FP32 FLOP
+per launch over its duration measured with HIP events on its stream, against
+the 157.3 TFLOP/s FP32 vector peak), the same figures for every stage, and
+the FP64 CPU oracle timed on a bounded pixel sample of the same workload on
+the host cores.
 """
 import argparse
 import json
@@ -21,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "primary Mrays/s + % FP32 VALU peak; adjoint grads/s vs FD at rel err 1e-3"
+WORKLOAD = "mandelbulb_n8_1920x1080_8views"
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU
 
 # Algorithmic FLOP per unit (FMA = 2, add/mul = 1, elementary function = 1):
@@ -30,17 +35,17 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU
 #   tail 6, step update and stop test 4).
 FLOP_PER_BODY = {"julia": 24.0, "bulb": 30.0}
 FLOP_PER_EVAL = 16.0
+STAGES = ("primary_march", "normals", "shadow_march")
 
 
-def algorithmic_flop(kind, counters):
-    evals = counters[1].astype("float64").sum()
-    bodies = counters[2].astype("float64").sum()
-    return FLOP_PER_BODY[kind] * bodies + FLOP_PER_EVAL * evals, evals, bodies
+def stage_flop(kind, counters):
+    """Algorithmic FLOP of each stage from the per-pixel counter planes
+    (1/2 primary evaluations/bodies, 4/5 normal taps, 6/7 shadow rays)."""
+    c = counters.astype("float64")
+    return [FLOP_PER_BODY[kind] * c[bo].sum() + FLOP_PER_EVAL * c[ev].sum() for ev, bo in ((1, 2), (4, 5), (6, 7))]
 
 
 def cpu_baseline(jobs, stride):
-    import numpy as np
-
     import workloads as W
     from oracle import oracle as orc
 
@@ -64,6 +69,7 @@ def main():
     ap.add_argument("--mode", choices=["batch", "single"], default="batch")
     ap.add_argument("--cpu-stride", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch configuration")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (to scale HBM byte counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -91,11 +97,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n * 4}), flush=True)
         return
+
     jobs = W.bulb_views()
     rays = sum(j["camera"]["width"] * j["camera"]["height"] for j in jobs)
     frames = [frt.alloc_frame(j, dev) for j in jobs]
     ws = frt.alloc_workspace(len(jobs), dev)
-    stream = torch.cuda.current_stream(dev)
 
     def step():
         if args.mode == "batch":
@@ -104,39 +110,59 @@ def main():
             for j, f in zip(jobs, frames):
                 frt.render(j, dev, out=f, workspace=ws)
 
+    tuned = None
+    if not args.no_tune:
+        from paper_2102_01747_amd import autotune
+
+        tuned = autotune.tune(jobs, batch=(args.mode == "batch"), reps=3, passes=2, device=dev)
+
     # algorithmic work of one step, from the per-pixel counters (untimed)
     cframes = [frt.alloc_frame(j, dev, counters=True) for j in jobs]
     frt.render_batch(jobs, dev, outs=cframes, workspace=ws)
     torch.cuda.synchronize()
-    flop = 0.0
+    flops = np.zeros(3)
     for f in cframes:
-        fl, _, _ = algorithmic_flop("bulb", f["counters"].cpu().numpy().view(np.uint32))
-        flop += fl
+        flops += np.array(stage_flop("bulb", f["counters"].cpu().numpy().view(np.uint32)))
     del cframes
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(stream)
+    for _ in range(args.steps):
         step()
-        ends[k].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     ms_step = wall * 1e3 / args.steps
-    launch_ms = float(np.mean(ms))
-    achieved = flop / (launch_ms * 1e-3) / 1e12
+
+    # per-kernel durations: HIP events recorded by the library on the launch
+    # stream around each stage, over the same number of steps
+    frt.set_stage_timing(True)
+    per_stage = np.zeros(3)
+    for _ in range(args.steps):
+        if args.mode == "batch":
+            step()
+            per_stage += np.array(frt.stage_times())
+        else:
+            for j, f in zip(jobs, frames):
+                frt.render(j, dev, out=f, workspace=ws)
+                per_stage += np.array(frt.stage_times())
+    frt.set_stage_timing(False)
+    per_stage /= args.steps
+    stages = {}
+    for k, name in enumerate(STAGES):
+        ach = flops[k] / (per_stage[k] * 1e-3) / 1e12 if per_stage[k] > 0 else 0.0
+        stages[name] = {"ms": float(per_stage[k]), "flop": float(flops[k]), "achieved_tflops": ach,
+                        "frac": ach / FP32_VECTOR_PEAK_TFLOPS}
+    dom = max(STAGES, key=lambda n: stages[n]["ms"])
+    achieved = stages[dom]["achieved_tflops"]
 
     traffic = None
     if os.path.exists(args.traffic):
         try:
             with open(args.traffic) as fh:
                 tr = json.load(fh)
-            if tr.get("workload") == "mandelbulb_n8_1920x1080_8views" and tr.get("mode") == args.mode:
+            if tr.get("workload") == WORKLOAD and tr.get("stage") == dom:
                 traffic = tr.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
@@ -154,13 +180,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "mandelbulb_n8_1920x1080_8views", "views": len(jobs), "width": 1920, "height": 1080,
-                   "power": 8, "max_iter": 10, "max_steps": 512, "eps_rel": 5e-4, "normals": "central",
-                   "shadow": True, "launch": args.mode, "primary_rays_per_step": rays},
+        "config": {"workload": WORKLOAD, "views": len(jobs), "width": 1920, "height": 1080, "power": 8,
+                   "max_iter": 10, "max_steps": 512, "eps_rel": 5e-4, "normals": "central", "shadow": True,
+                   "launch": args.mode, "primary_rays_per_step": rays},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "trace_kernel (persistent, Mandelbulb integer power)",
-                     "flop_per_launch": flop, "launch_ms": launch_ms},
+                     "kernel": "normal_kernel<bulb8>" if dom == "normals" else "march_kernel<bulb8>",
+                     "stage": dom, "flop_per_launch": stages[dom]["flop"], "launch_ms": stages[dom]["ms"]},
+        "stages": stages,
+        "whole_path_tflops": float(flops.sum() / (ms_step * 1e-3) / 1e12),
+        "launch_config": tuned["config"] if tuned else "library defaults",
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(jobs, args.cpu_stride)

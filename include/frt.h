@@ -38,9 +38,13 @@
  *                          bit 3: shadowed (the shadow ray hit);
  *                          bit 4: depth not refined (first sample or
  *                          running out of steps)
- *   counters uint32[4][P]  optional (NULL to skip): primary march samples,
- *                          distance evaluations in total, orbit bodies in
- *                          total, escape count at the last march sample
+ *   counters uint32[8][P]  optional (NULL to skip), per pixel:
+ *                          0 primary march samples,
+ *                          1 distance evaluations of the primary ray (cut
+ *                            face, march, refinement), 2 their orbit bodies,
+ *                          3 escape count at the last primary march sample,
+ *                          4 normal-tap evaluations, 5 their orbit bodies,
+ *                          6 shadow-ray evaluations, 7 their orbit bodies
  */
 #ifndef FRT_H
 #define FRT_H
@@ -207,15 +211,25 @@ frt_status frt_math_eval(int32_t func, const float* x, const float* y, float* ou
  * block: 64, 128, 256 or 512 threads; chunk: rays taken from the queue per
  * refill, a multiple of 64 in [64, 4096]; waves_per_simd: resident waves per
  * SIMD the grid is sized for, [1, 8] (0 = occupancy limit);
- * bodies_per_trip: orbit bodies a lane advances per trip of the wave loop
- * before lanes whose estimate is done take their next step, [1, 64];
+ * orbit_lanes: the wave keeps advancing orbits while at least this many
+ * of its lanes still iterate, then lanes whose estimate is done take their
+ * next step (1: every orbit runs to its end first), [1, 64];
  * rare_lanes: number of waiting lanes that triggers shading, output writes
  * and refill, [1, 64].  The setting is process-wide and applies to launches
  * that start after the call.                                               */
 frt_status frt_autotune_set(int32_t kernel_variant, int32_t block, int32_t chunk, int32_t waves_per_simd,
-                            int32_t bodies_per_trip, int32_t rare_lanes);
+                            int32_t orbit_lanes, int32_t rare_lanes);
 frt_status frt_autotune_get(int32_t kernel_variant, int32_t* block, int32_t* chunk, int32_t* waves_per_simd,
-                            int32_t* bodies_per_trip, int32_t* rare_lanes);
+                            int32_t* orbit_lanes, int32_t* rare_lanes);
+
+/* Per-stage timing of the forward pass.  While enabled (enable = 1), each
+ * frt_render / non-graph frt_render_batch call records HIP events on its
+ * stream around its three kernels; frt_stage_times() waits for the last
+ * call's events and writes the durations in ms of the primary march, the
+ * normal kernel and the shadow march (0 when no shadow rays) to ms[0..2].
+ * Process-wide; meant for benchmarking, not for concurrent streams.        */
+frt_status frt_set_stage_timing(int32_t enable);
+frt_status frt_stage_times(float* ms);
 
 /* Drop every captured batch graph; the next graph call captures again.     */
 frt_status frt_graph_reset(void);

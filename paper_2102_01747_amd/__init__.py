@@ -91,6 +91,10 @@ def lib():
         L.frt_distance.restype = ctypes.c_int
         L.frt_math_eval.argtypes = [i32, vp, vp, vp, ctypes.c_int64, vp]
         L.frt_math_eval.restype = ctypes.c_int
+        L.frt_set_stage_timing.argtypes = [i32]
+        L.frt_set_stage_timing.restype = ctypes.c_int
+        L.frt_stage_times.argtypes = [P(ctypes.c_float)]
+        L.frt_stage_times.restype = ctypes.c_int
         L.frt_status_string.argtypes = [ctypes.c_int]
         L.frt_status_string.restype = ctypes.c_char_p
         L.frt_last_error.argtypes = []
@@ -156,7 +160,7 @@ def alloc_frame(job, device="cuda", counters=False):
           "colour": torch.empty(3, P, device=dev, dtype=torch.float32),
           "status": torch.empty(P, device=dev, dtype=torch.uint8)}
     if counters:
-        fr["counters"] = torch.empty(4, P, device=dev, dtype=torch.int32)   # read as uint32
+        fr["counters"] = torch.empty(8, P, device=dev, dtype=torch.int32)   # read as uint32
     return fr
 
 
@@ -233,18 +237,29 @@ def math_eval(func, x, y=None, device="cuda"):
     return out
 
 
-def autotune_set(variant, block, chunk, waves_per_simd=0, bodies_per_trip=1, rare_lanes=16):
+def autotune_set(variant, block, chunk, waves_per_simd=0, orbit_lanes=8, rare_lanes=16):
     v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
-    _check(lib().frt_autotune_set(v, int(block), int(chunk), int(waves_per_simd), int(bodies_per_trip),
+    _check(lib().frt_autotune_set(v, int(block), int(chunk), int(waves_per_simd), int(orbit_lanes),
                                   int(rare_lanes)))
 
 
 def autotune_get(variant):
-    """(block, chunk, waves_per_simd, bodies_per_trip, rare_lanes) of a kernel variant."""
+    """(block, chunk, waves_per_simd, orbit_lanes, rare_lanes) of a kernel variant."""
     v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     vals = [ctypes.c_int32() for _ in range(5)]
     _check(lib().frt_autotune_get(v, *[ctypes.byref(x) for x in vals]))
     return tuple(x.value for x in vals)
+
+
+def set_stage_timing(enable):
+    _check(lib().frt_set_stage_timing(int(bool(enable))))
+
+
+def stage_times():
+    """(primary march, normals, shadow march) durations in ms of the last call."""
+    ms = (ctypes.c_float * 3)()
+    _check(lib().frt_stage_times(ms))
+    return tuple(float(x) for x in ms)
 
 
 def graph_reset():

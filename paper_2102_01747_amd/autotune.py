@@ -21,11 +21,11 @@ from . import VARIANTS, alloc_frame, alloc_workspace, autotune_get, autotune_set
 SPACE = {
     "block": [64, 128, 256, 512],
     "chunk": [64, 128, 256, 512, 1024],
-    "waves_per_simd": [1, 2, 3, 4, 0],
-    "bodies_per_trip": [1, 2, 3, 4, 6, 10],
+    "waves_per_simd": [2, 4, 6, 8, 0],
+    "orbit_lanes": [1, 4, 8, 16, 24, 32, 48],
     "rare_lanes": [2, 4, 8, 16, 32, 48],
 }
-KEYS = ["block", "chunk", "waves_per_simd", "bodies_per_trip", "rare_lanes"]
+KEYS = ["block", "chunk", "waves_per_simd", "orbit_lanes", "rare_lanes"]
 
 
 def variant_of(jobs):

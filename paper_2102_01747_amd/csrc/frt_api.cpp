@@ -33,21 +33,39 @@ frt_status hip_fail(hipError_t e, const char* what) {
     return fail(FRT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// ----------------------------------------------------------- stage timing
+// When enabled, every forward call records four events on its stream (before
+// the primary march, the normal kernel and the shadow march, and after the
+// last); frt_stage_times() reads the last call's stage durations.
+std::mutex g_time_mu;
+bool g_timing = false;
+hipEvent_t g_marks[4] = {nullptr, nullptr, nullptr, nullptr};
+bool g_marks_recorded = false;
+
+hipEvent_t* timing_marks() {
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    if (!g_timing) return nullptr;
+    for (hipEvent_t& ev : g_marks)
+        if (!ev && hipEventCreate(&ev) != hipSuccess) return nullptr;
+    g_marks_recorded = true;
+    return g_marks;
+}
+
 // ---------------------------------------------------------------- tuning
 struct Tune {
     int block;
     int chunk;
     int waves_per_simd;
-    int bodies_per_trip;
+    int orbit_lanes;
     int rare_lanes;
 };
 std::mutex g_mu;
 Tune g_tune[frt::kNumVariants] = {
-    {128, 64, 0, 6, 16},   // Julia
-    {128, 64, 0, 6, 16},   // Mandelbulb, real power
-    {128, 64, 0, 6, 16},   // Mandelbulb, integer power
-    {128, 64, 0, 6, 16},   // mixed
-    {128, 64, 0, 6, 16},   // Mandelbulb, n = 8
+    {64, 256, 0, 8, 16},   // Julia
+    {64, 256, 0, 8, 16},   // Mandelbulb, real power
+    {64, 256, 0, 8, 16},   // Mandelbulb, integer power
+    {64, 256, 0, 8, 16},   // mixed
+    {64, 256, 0, 8, 16},   // Mandelbulb, n = 8
 };
 
 int device_cus() {
@@ -82,7 +100,7 @@ bool make_cfg(const void* kernel, int variant, LaunchCfg& cfg, std::string& why)
     cfg.normal_grid = 8 * device_cus();
     cfg.block = t.block;
     cfg.chunk = t.chunk;
-    cfg.bodies_per_trip = t.bodies_per_trip;
+    cfg.orbit_lanes = t.orbit_lanes;
     cfg.rare_lanes = t.rare_lanes;
     return true;
 }
@@ -330,7 +348,7 @@ frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_
     LaunchCfg cfg;
     if (!make_cfg(frt::trace_kernel_symbol(var, false), var, cfg, why)) return fail(FRT_EHIP, why);
     hipError_t e = frt::launch_trace(var, false, cfg, nullptr, J, static_cast<WorkspaceHeader*>(workspace),
-                                     J.shadow != 0, static_cast<hipStream_t>(stream));
+                                     J.shadow != 0, static_cast<hipStream_t>(stream), timing_marks());
     if (e != hipSuccess) return hip_fail(e, "trace launch");
     return FRT_OK;
 }
@@ -370,7 +388,7 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
     if (!make_cfg(frt::trace_kernel_symbol(var, true), var, cfg, why)) return fail(FRT_EHIP, why);
     WorkspaceHeader* dhdr = static_cast<WorkspaceHeader*>(workspace);
     if (!use_graph) {
-        hipError_t e = frt::launch_trace(var, true, cfg, dev_jobs, table[0], dhdr, any_shadow, st);
+        hipError_t e = frt::launch_trace(var, true, cfg, dev_jobs, table[0], dhdr, any_shadow, st, timing_marks());
         if (e != hipSuccess) return hip_fail(e, "trace launch");
         return FRT_OK;
     }
@@ -381,7 +399,7 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
     for (const GraphEntry& g : g_graphs) {
         if (g.workspace == workspace && g.variant == var && g.device == dev && g.any_shadow == any_shadow &&
             g.cfg.grid == cfg.grid && g.cfg.block == cfg.block && g.cfg.chunk == cfg.chunk &&
-            g.cfg.bodies_per_trip == cfg.bodies_per_trip && g.cfg.rare_lanes == cfg.rare_lanes) {
+            g.cfg.orbit_lanes == cfg.orbit_lanes && g.cfg.rare_lanes == cfg.rare_lanes) {
             exec = g.exec;
             break;
         }
@@ -471,24 +489,24 @@ frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float*
 }
 
 frt_status frt_autotune_set(int32_t kernel_variant, int32_t block, int32_t chunk, int32_t waves_per_simd,
-                            int32_t bodies_per_trip, int32_t rare_lanes) {
+                            int32_t orbit_lanes, int32_t rare_lanes) {
     g_last_error.clear();
     if (kernel_variant < 0 || kernel_variant >= frt::kNumVariants) return fail(FRT_EINVAL, "unknown kernel_variant");
     if (block != 64 && block != 128 && block != 256 && block != 512) return fail(FRT_EINVAL, "block must be 64..512");
     if (chunk < 64 || chunk > 4096 || chunk % 64 != 0) return fail(FRT_EINVAL, "chunk must be a multiple of 64 in [64, 4096]");
     if (waves_per_simd < 0 || waves_per_simd > 8) return fail(FRT_EINVAL, "waves_per_simd must be in [0, 8]");
-    if (bodies_per_trip < 1 || bodies_per_trip > 64) return fail(FRT_EINVAL, "bodies_per_trip must be in [1, 64]");
+    if (orbit_lanes < 1 || orbit_lanes > 64) return fail(FRT_EINVAL, "orbit_lanes must be in [1, 64]");
     if (rare_lanes < 1 || rare_lanes > 64) return fail(FRT_EINVAL, "rare_lanes must be in [1, 64]");
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tune[kernel_variant] = Tune{block, chunk, waves_per_simd, bodies_per_trip, rare_lanes};
+    g_tune[kernel_variant] = Tune{block, chunk, waves_per_simd, orbit_lanes, rare_lanes};
     return FRT_OK;
 }
 
 frt_status frt_autotune_get(int32_t kernel_variant, int32_t* block, int32_t* chunk, int32_t* waves_per_simd,
-                            int32_t* bodies_per_trip, int32_t* rare_lanes) {
+                            int32_t* orbit_lanes, int32_t* rare_lanes) {
     g_last_error.clear();
     if (kernel_variant < 0 || kernel_variant >= frt::kNumVariants) return fail(FRT_EINVAL, "unknown kernel_variant");
-    if (!block || !chunk || !waves_per_simd || !bodies_per_trip || !rare_lanes) {
+    if (!block || !chunk || !waves_per_simd || !orbit_lanes || !rare_lanes) {
         return fail(FRT_EINVAL, "null output pointer");
     }
     std::lock_guard<std::mutex> lk(g_mu);
@@ -496,8 +514,31 @@ frt_status frt_autotune_get(int32_t kernel_variant, int32_t* block, int32_t* chu
     *block = t.block;
     *chunk = t.chunk;
     *waves_per_simd = t.waves_per_simd;
-    *bodies_per_trip = t.bodies_per_trip;
+    *orbit_lanes = t.orbit_lanes;
     *rare_lanes = t.rare_lanes;
+    return FRT_OK;
+}
+
+frt_status frt_set_stage_timing(int32_t enable) {
+    g_last_error.clear();
+    if (enable != 0 && enable != 1) return fail(FRT_EINVAL, "enable must be 0 or 1");
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    g_timing = enable == 1;
+    g_marks_recorded = false;
+    return FRT_OK;
+}
+
+frt_status frt_stage_times(float* ms) {
+    g_last_error.clear();
+    if (!ms) return fail(FRT_EINVAL, "null output");
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    if (!g_timing || !g_marks_recorded) return fail(FRT_EINVAL, "stage timing is off or nothing was recorded");
+    for (int k = 0; k < 3; ++k) {
+        hipError_t e = hipEventSynchronize(g_marks[k + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        e = hipEventElapsedTime(&ms[k], g_marks[k], g_marks[k + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    }
     return FRT_OK;
 }
 

@@ -12,7 +12,7 @@ struct LaunchCfg {
     int normal_grid;      // workgroups of the normal kernel (grid-stride)
     int block;            // threads per workgroup, multiple of 64
     int chunk;            // rays claimed from the queue per refill
-    int bodies_per_trip;  // orbit bodies a lane advances per loop trip
+    int orbit_lanes;      // keep iterating orbits while this many lanes still iterate
     int rare_lanes;       // waiting lanes that trigger shading / refill
 };
 
@@ -20,8 +20,11 @@ struct LaunchCfg {
 // the primary march, the normal kernel and (if any_shadow) the shadow march.
 // batch = false reads the job from `job1` (kernel argument); batch = true
 // reads `jobs` (device table) and the ray count from `hdr`.
+// marks[0..3] (optional, may be null): events recorded on `stream` before the
+// primary march, before the normal kernel, before the shadow march and after
+// the last kernel.
 hipError_t launch_trace(int variant, bool batch, const LaunchCfg& cfg, const JobDev* jobs, const JobDev& job1,
-                        WorkspaceHeader* hdr, bool any_shadow, hipStream_t stream);
+                        WorkspaceHeader* hdr, bool any_shadow, hipStream_t stream, hipEvent_t* marks = nullptr);
 const void* trace_kernel_symbol(int variant, bool batch);
 
 // Point queries (frt_query.hip).

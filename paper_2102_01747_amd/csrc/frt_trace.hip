@@ -12,11 +12,12 @@
 //      hit, the normal, and Lambert shading assuming the point is lit;
 //   3. march_kernel<shadow>: one shadow ray toward the light from every lit
 //      hit; on a hit the pixel is marked shadowed and keeps only ambient light.
-// The two march kernels are persistent: each wave runs one loop in which every
-// busy lane advances its orbit by up to `bodies_per_trip` bodies (Eq. 3-4), so
-// a lane whose orbit escapes early does not wait for the slowest lane; lanes
+// The two march kernels are persistent: each wave runs one loop in which the
+// busy lanes advance their orbits (Eq. 3-4) while at least `orbit_lanes` of
+// them still iterate, so the wave does not wait for its slowest orbit: lanes
 // whose estimate is done take their march / refinement step in place and
-// start the next sample; and when `rare_lanes` lanes wait (or none is busy)
+// start the next sample, stragglers resume next trip; and when `rare_lanes`
+// lanes wait (or none is busy)
 // finished rays are written and idle lanes refill from a global ray queue --
 // one atomic claims `chunk` ray indices, handed out by ballot + mbcnt.  A wave
 // leaves its loop when the ballot of busy lanes is empty and the queue is
@@ -31,6 +32,8 @@ namespace frt {
 
 // Refinement stops once the root bracket is narrower than eps(t) / 32.
 constexpr float kRefineTol = 1.0f / 32.0f;
+// Upper bound on orbit bodies per loop trip (keeps finished rays flowing).
+constexpr int kMaxBodiesPerTrip = 64;
 
 template <int VAR> struct OrbitOf;
 template <> struct OrbitOf<kVarJulia> { using T = JuliaOrbit; };
@@ -150,15 +153,19 @@ enum MarchPhase : int { kIdle = 0, kCut = 1, kMarch = 2, kRefine = 3, kDone = 4 
 template <int VAR, bool BATCH, bool SHADOW>
 __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                                                     WorkspaceHeader* __restrict__ hdr, int chunk,
-                                                    int bodies_per_trip, int rare_lanes) {
+                                                    int orbit_lanes, int rare_lanes) {
     using Orbit = typename OrbitOf<VAR>::T;
-    unsigned long long* queue = &hdr->queue[SHADOW ? 1 : 0];
+    unsigned long long* queues = hdr->queue[SHADOW ? 1 : 0];
     int n_jobs = 1;
     unsigned long long total_rays = static_cast<unsigned long long>(job1.ray_count);
     if constexpr (BATCH) {
         n_jobs = hdr->n_jobs;
         total_rays = hdr->total_rays;
     }
+    // segments of the ray index space (multiples of 64 rays); a wave starts on
+    // the segment of its workgroup and moves on when that one is drained
+    const unsigned long long seg = ((total_rays + kQueues * 64ull - 1) / (kQueues * 64ull)) * 64ull;
+    int qi = static_cast<int>(blockIdx.x % kQueues), q_tries = 0;
     unsigned long long q_next = 0, q_end = 0;   // wave-uniform queue window
     bool drained = false;
 
@@ -205,6 +212,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                         J.counters[NP + pix] = evals;
                         J.counters[2 * NP + pix] = bodies;
                         J.counters[3 * NP + pix] = static_cast<unsigned>(hit_it);
+                        for (int k = 4; k < kCounterPlanes; ++k) J.counters[k * NP + pix] = 0u;
                     }
                 } else {
                     if (status & kFlagShadowed) {
@@ -214,8 +222,8 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                         J.colour[2 * NP + pix] = J.albedo[2] * J.k_a;
                     }
                     if (J.counters) {
-                        J.counters[NP + pix] += evals;
-                        J.counters[2 * NP + pix] += bodies;
+                        J.counters[6 * NP + pix] = evals;
+                        J.counters[7 * NP + pix] = bodies;
                     }
                 }
                 phase = kIdle;
@@ -224,15 +232,18 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
             unsigned long long idle = __ballot(phase == kIdle);
             while (idle != 0ull && !drained) {
                 if (q_next >= q_end) {
+                    const unsigned long long s0 = static_cast<unsigned long long>(qi) * seg;
+                    const unsigned long long s1 = min(s0 + seg, total_rays);
                     unsigned long long base = 0;
-                    if (__lane_id() == 0) base = atomicAdd(queue, static_cast<unsigned long long>(chunk));
-                    base = bcast_first(base);
-                    if (base >= total_rays) {
-                        drained = true;
-                        break;
+                    if (__lane_id() == 0) base = atomicAdd(&queues[qi], static_cast<unsigned long long>(chunk));
+                    base = s0 + bcast_first(base);
+                    if (base >= s1) {   // segment drained: try the next one
+                        qi = (qi + 1) % kQueues;
+                        if (++q_tries == kQueues) drained = true;
+                        continue;
                     }
                     q_next = base;
-                    q_end = min(base + static_cast<unsigned long long>(chunk), total_rays);
+                    q_end = min(base + static_cast<unsigned long long>(chunk), s1);
                 }
                 const unsigned rank = lane_rank(idle);
                 const unsigned long long avail = q_end - q_next;
@@ -264,10 +275,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                             J.colour[2 * NP + p] = 0.0f;
                             J.status[p] = kMissBounds;
                             if (J.counters) {
-                                J.counters[p] = 0u;
-                                J.counters[NP + p] = 0u;
-                                J.counters[2 * NP + p] = 0u;
-                                J.counters[3 * NP + p] = 0u;
+                                for (int k = 0; k < kCounterPlanes; ++k) J.counters[k * NP + p] = 0u;
                             }
                         }
                     } else if (J.shadow && (J.status[p] & 7) >= kHit) {
@@ -315,8 +323,16 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
         }
 
         // -------------------------------------------------- orbit bodies
+        // Iterate while at least `orbit_lanes` lanes still iterate (and at
+        // least once); lanes whose orbit ends wait for the step below, the
+        // stragglers carry their orbit state into the next trip.
+        for (int b = 0; b < kMaxBodiesPerTrip; ++b) {
+            const bool iter = (phase == kCut || phase == kMarch || phase == kRefine) && !orb.done(P);
+            const int n_iter = __popcll(__ballot(iter));
+            if (n_iter == 0 || (b > 0 && n_iter < orbit_lanes)) break;
+            if (iter) orb.body(P);
+        }
         if (phase == kCut || phase == kMarch || phase == kRefine) {
-            for (int b = 0; b < bodies_per_trip && !orb.done(P); ++b) orb.body(P);
             if (orb.done(P)) {
                 const JobDev& J = job_ref<BATCH>(jobs, job1, jb);
                 const DEResult de = orb.result();
@@ -481,29 +497,41 @@ __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ 
         J.colour[NP + p] = J.albedo[1] * lam;
         J.colour[2 * NP + p] = J.albedo[2] * lam;
         if (J.counters && evals) {
-            J.counters[NP + p] += evals;
-            J.counters[2 * NP + p] += bodies;
+            J.counters[4 * NP + p] = evals;
+            J.counters[5 * NP + p] = bodies;
         }
     }
 }
 
 __global__ void reset_queue_kernel(WorkspaceHeader* hdr) {
-    if (threadIdx.x < 2) hdr->queue[threadIdx.x] = 0ull;
+    if (threadIdx.x < 2 * kQueues) hdr->queue[threadIdx.x / kQueues][threadIdx.x % kQueues] = 0ull;
+}
+
+static hipError_t mark(hipEvent_t* marks, int k, hipStream_t stream) {
+    return marks ? hipEventRecord(marks[k], stream) : hipSuccess;
 }
 
 template <int VAR, bool BATCH>
 static hipError_t launch_var(const LaunchCfg& cfg, const JobDev* jobs, const JobDev& job1, WorkspaceHeader* hdr,
-                             bool any_shadow, hipStream_t stream) {
+                             bool any_shadow, hipStream_t stream, hipEvent_t* marks) {
+    hipError_t e = mark(marks, 0, stream);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((march_kernel<VAR, BATCH, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, jobs, job1,
-                       hdr, cfg.chunk, cfg.bodies_per_trip, cfg.rare_lanes);
-    hipError_t e = hipGetLastError();
+                       hdr, cfg.chunk, cfg.orbit_lanes, cfg.rare_lanes);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = mark(marks, 1, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((normal_kernel<VAR, BATCH>), dim3(cfg.normal_grid), dim3(256), 0, stream, jobs, job1, hdr);
     e = hipGetLastError();
-    if (e != hipSuccess || !any_shadow) return e;
-    hipLaunchKernelGGL((march_kernel<VAR, BATCH, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, jobs, job1,
-                       hdr, cfg.chunk, cfg.bodies_per_trip, cfg.rare_lanes);
-    return hipGetLastError();
+    if (e == hipSuccess) e = mark(marks, 2, stream);
+    if (e != hipSuccess) return e;
+    if (any_shadow) {
+        hipLaunchKernelGGL((march_kernel<VAR, BATCH, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, jobs, job1,
+                           hdr, cfg.chunk, cfg.orbit_lanes, cfg.rare_lanes);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return mark(marks, 3, stream);
 }
 
 template <int VAR, bool BATCH>
@@ -522,26 +550,26 @@ const void* trace_kernel_symbol(int variant, bool batch) {
 }
 
 hipError_t launch_trace(int variant, bool batch, const LaunchCfg& cfg, const JobDev* jobs, const JobDev& job1,
-                        WorkspaceHeader* hdr, bool any_shadow, hipStream_t stream) {
+                        WorkspaceHeader* hdr, bool any_shadow, hipStream_t stream, hipEvent_t* marks) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, stream, hdr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (variant) {
         case kVarJulia:
-            return batch ? launch_var<kVarJulia, true>(cfg, jobs, job1, hdr, any_shadow, stream)
-                         : launch_var<kVarJulia, false>(cfg, jobs, job1, hdr, any_shadow, stream);
+            return batch ? launch_var<kVarJulia, true>(cfg, jobs, job1, hdr, any_shadow, stream, marks)
+                         : launch_var<kVarJulia, false>(cfg, jobs, job1, hdr, any_shadow, stream, marks);
         case kVarBulbReal:
-            return batch ? launch_var<kVarBulbReal, true>(cfg, jobs, job1, hdr, any_shadow, stream)
-                         : launch_var<kVarBulbReal, false>(cfg, jobs, job1, hdr, any_shadow, stream);
+            return batch ? launch_var<kVarBulbReal, true>(cfg, jobs, job1, hdr, any_shadow, stream, marks)
+                         : launch_var<kVarBulbReal, false>(cfg, jobs, job1, hdr, any_shadow, stream, marks);
         case kVarBulbInt:
-            return batch ? launch_var<kVarBulbInt, true>(cfg, jobs, job1, hdr, any_shadow, stream)
-                         : launch_var<kVarBulbInt, false>(cfg, jobs, job1, hdr, any_shadow, stream);
+            return batch ? launch_var<kVarBulbInt, true>(cfg, jobs, job1, hdr, any_shadow, stream, marks)
+                         : launch_var<kVarBulbInt, false>(cfg, jobs, job1, hdr, any_shadow, stream, marks);
         case kVarBulb8:
-            return batch ? launch_var<kVarBulb8, true>(cfg, jobs, job1, hdr, any_shadow, stream)
-                         : launch_var<kVarBulb8, false>(cfg, jobs, job1, hdr, any_shadow, stream);
+            return batch ? launch_var<kVarBulb8, true>(cfg, jobs, job1, hdr, any_shadow, stream, marks)
+                         : launch_var<kVarBulb8, false>(cfg, jobs, job1, hdr, any_shadow, stream, marks);
         default:
-            return batch ? launch_var<kVarMixed, true>(cfg, jobs, job1, hdr, any_shadow, stream)
-                         : launch_var<kVarMixed, false>(cfg, jobs, job1, hdr, any_shadow, stream);
+            return batch ? launch_var<kVarMixed, true>(cfg, jobs, job1, hdr, any_shadow, stream, marks)
+                         : launch_var<kVarMixed, false>(cfg, jobs, job1, hdr, any_shadow, stream, marks);
     }
 }
 
