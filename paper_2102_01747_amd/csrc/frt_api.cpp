@@ -80,24 +80,48 @@ int device_cus() {
     return cached[dev];
 }
 
-bool make_cfg(const void* kernel, int variant, LaunchCfg& cfg, std::string& why) {
+bool make_cfg(const void* kernel, int variant, long long total_rays, LaunchCfg& cfg, std::string& why) {
     Tune t;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         t = g_tune[variant];
     }
+    // occupancy of (kernel, block) on this device, queried once
+    struct OccEntry {
+        const void* kernel;
+        int block;
+        int device;
+        int per_cu;
+    };
+    static std::mutex occ_mu;
+    static std::vector<OccEntry> occ_cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, t.block, 0);
-    if (e != hipSuccess || per_cu <= 0) {
-        why = std::string("occupancy query failed: ") + hipGetErrorString(e);
-        return false;
+    {
+        std::lock_guard<std::mutex> lk(occ_mu);
+        for (const OccEntry& o : occ_cache)
+            if (o.kernel == kernel && o.block == t.block && o.device == dev) per_cu = o.per_cu;
+    }
+    if (per_cu == 0) {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, t.block, 0);
+        if (e != hipSuccess || per_cu <= 0) {
+            why = std::string("occupancy query failed: ") + hipGetErrorString(e);
+            return false;
+        }
+        std::lock_guard<std::mutex> lk(occ_mu);
+        occ_cache.push_back(OccEntry{kernel, t.block, dev, per_cu});
     }
     if (t.waves_per_simd > 0) {
         const int want = (t.waves_per_simd * 4 * 64) / t.block;   // 4 SIMDs per CU
         per_cu = std::max(1, std::min(per_cu, want));
     }
-    cfg.grid = per_cu * device_cus();
-    cfg.normal_grid = 8 * device_cus();
+    // never more waves than 64-ray tiles to trace
+    const long long tiles = std::max(1ll, (total_rays + 63) / 64);
+    const long long waves_per_block = t.block / 64;
+    const long long need = (tiles + waves_per_block - 1) / waves_per_block;
+    cfg.grid = static_cast<int>(std::min<long long>(static_cast<long long>(per_cu) * device_cus(), need));
+    cfg.normal_grid = static_cast<int>(std::min<long long>(8ll * device_cus(), (total_rays + 255) / 256));
     cfg.block = t.block;
     cfg.chunk = t.chunk;
     cfg.orbit_lanes = t.orbit_lanes;
@@ -346,7 +370,7 @@ frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_
     pack(cam, frac, planes, n_planes, march, out, 0, J);
     const int var = variant_of(J);
     LaunchCfg cfg;
-    if (!make_cfg(frt::trace_kernel_symbol(var, false), var, cfg, why)) return fail(FRT_EHIP, why);
+    if (!make_cfg(frt::trace_kernel_symbol(var, false), var, J.ray_count, cfg, why)) return fail(FRT_EHIP, why);
     hipError_t e = frt::launch_trace(var, false, cfg, nullptr, J, static_cast<WorkspaceHeader*>(workspace),
                                      J.shadow != 0, static_cast<hipStream_t>(stream), timing_marks());
     if (e != hipSuccess) return hip_fail(e, "trace launch");
@@ -385,7 +409,7 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
     const JobDev* dev_jobs = reinterpret_cast<const JobDev*>(static_cast<char*>(workspace) + sizeof(WorkspaceHeader));
     std::string why;
     LaunchCfg cfg;
-    if (!make_cfg(frt::trace_kernel_symbol(var, true), var, cfg, why)) return fail(FRT_EHIP, why);
+    if (!make_cfg(frt::trace_kernel_symbol(var, true), var, begin, cfg, why)) return fail(FRT_EHIP, why);
     WorkspaceHeader* dhdr = static_cast<WorkspaceHeader*>(workspace);
     if (!use_graph) {
         hipError_t e = frt::launch_trace(var, true, cfg, dev_jobs, table[0], dhdr, any_shadow, st, timing_marks());

@@ -7,7 +7,11 @@ rather than by the method:
   - an 8-neighbour has a different oracle hit/miss or cut-face outcome;
   - either side ran out of steps, or the oracle's root bracket closed on a
     jump of the estimate (no smooth root there);
-  - the escape count at the last march sample differs between the sides;
+  - the march took a different number of steps on the two sides, or the
+    escape count at the last march sample differs: the stop test d < eps
+    was decided by rounding at some sample, so the two sides refine
+    different brackets, which may hold different crossings of a thin
+    eps-region (several results are correct there);
   - the ray grazes the surface (|N . dir| < 0.05).
 Depth tolerance: 2 eps(t*).  Normal tolerance: 1e-3 rad, measured against
 the oracle's normal evaluated at the GPU's own hit point (which separates
@@ -113,6 +117,7 @@ def compare(orc, job, g, o, neigh_diff, pixels=None):
     B |= (gc == 4) | (oc == 4) | ((os_ & 32) != 0)
     if "counters" in g:
         B |= (g["counters"][3].astype(np.int64) != o["hit_iters"])
+        B |= (g["counters"][0].astype(np.int64) != o["steps"])
     on = o["normal"].T
     B |= ohit & (np.abs(np.einsum("ij,ij->i", on, dirs)) < 0.05)
     both = ghit & ohit & ~B

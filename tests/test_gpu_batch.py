@@ -1,0 +1,144 @@
+"""Batched persistent launch: 64 uneven quaternion Julia renders (seeded c,
+cut plane, resolution, iteration count and eps) drained by one launch per
+kernel, with and without HIP-graph replay, against one-by-one renders and
+the FP64 oracle."""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from parity import assert_parity, compare, neighbour_flags, neighbourhood_pixels, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def frt():
+    import paper_2102_01747_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def batch_jobs():
+    return W.julia_batch()
+
+
+def _same(a, b):
+    """Fraction of pixels with identical status and depth."""
+    return float(np.mean((a["status"] == b["status"]) & (a["depth"] == b["depth"])))
+
+
+def test_batch_equals_one_by_one(frt, batch_jobs):
+    outs = frt.render_batch(batch_jobs, "cuda", counters=True)
+    singles = [frt.render(j, "cuda", counters=True) for j in batch_jobs]
+    torch.cuda.synchronize()
+    worst = 1.0
+    for k, (a, b) in enumerate(zip(outs, singles)):
+        a, b = to_numpy(a), to_numpy(b)
+        s = _same(a, b)
+        worst = min(worst, s)
+        assert s >= 0.9999, (k, s)
+    print("worst identical-pixel fraction over 64 jobs: %.6f" % worst)
+
+
+def test_batch_parity_against_oracle(frt, orc, batch_jobs):
+    outs = frt.render_batch(batch_jobs, "cuda", counters=True)
+    torch.cuda.synchronize()
+    checked = 0
+    for k, (job, fr) in enumerate(zip(batch_jobs, outs)):
+        g = to_numpy(fr)
+        cam = job["camera"]
+        W_, H = cam["width"], cam["height"]
+        if W_ * H <= 256 * 256:
+            o = orc.render(job)
+            nd = neighbour_flags(o["status"].reshape(H, W_)).ravel()
+            st = compare(orc, job, g, o, nd)
+        else:
+            pix = W.stratified_pixels(W_, H, 8, seed=k)
+            nb = neighbourhood_pixels(pix, W_, H)
+            o_nb = orc.render(job, pixels=nb.ravel())
+            s_nb = o_nb["status"].reshape(nb.shape)
+            hit_nb, cut_nb = (s_nb & 7) >= 2, (s_nb & 7) == 3
+            nd = np.any(hit_nb != hit_nb[:, 4:5], 1) | np.any(cut_nb != cut_nb[:, 4:5], 1)
+            o = {key: (v[..., 4::9] if v.ndim == 1 else v[:, 4::9]) for key, v in o_nb.items()}
+            gs = {key: (v[pix] if v.ndim == 1 else v[:, pix]) for key, v in g.items()}
+            st = compare(orc, job, gs, o, nd, pixels=pix)
+        if st["oracle_hits"] == 0 and st["gpu_hits"] == 0:
+            continue
+        assert_parity(st)
+        checked += 1
+    print("jobs with hits compared:", checked)
+    assert checked >= 10
+
+
+def test_graph_replay_matches_eager(frt, batch_jobs):
+    """Capture once, replay with changed parameters and with the program's
+    own eager work and synchronisations between replays; every replay must
+    equal a fresh eager render of the same jobs."""
+    jobs = copy.deepcopy(batch_jobs[:16])
+    frames = [frt.alloc_frame(j, "cuda") for j in jobs]
+    ref_frames = [frt.alloc_frame(j, "cuda") for j in jobs]
+    ws = frt.alloc_workspace(len(jobs), "cuda")
+    frt.graph_reset()
+    rng = np.random.default_rng(7)
+    for rep in range(4):
+        if rep > 0:
+            for j in jobs:   # new parameters between replays
+                j["fractal"]["c"] = W.f32v(np.array(j["fractal"]["c"]) + rng.normal(0, 0.01, 4))
+        frt.render_batch(jobs, "cuda", outs=frames, workspace=ws, use_graph=True)
+        junk = torch.randn(1 << 20, device="cuda")
+        junk = (junk * 2).sum()            # eager work on the same stream
+        torch.cuda.synchronize()
+        frt.render_batch(jobs, "cuda", outs=ref_frames, workspace=frt.alloc_workspace(len(jobs), "cuda"))
+        torch.cuda.synchronize()
+        for a, b in zip(frames, ref_frames):
+            a, b = to_numpy(a), to_numpy(b)
+            assert np.array_equal(a["status"], b["status"])
+            assert np.array_equal(a["depth"], b["depth"])
+            assert np.array_equal(a["colour"], b["colour"])
+    frt.graph_reset()
+
+
+def test_mixed_kind_batch(frt, orc):
+    jobs = [W.julia_view(width=120, height=90), W.bulb_view(0.3, 0.1, width=100, height=80),
+            W.bulb_view(1.3, -0.2, width=64, height=64, power=6.37, planes=[W.plane([0.1, 1, 0], 0.05)]),
+            W.julia_view(width=50, height=70, planes=[W.plane([0.3, 0.2, 1.0], 0.05)], shadow=True)]
+    outs = frt.render_batch(jobs, "cuda", counters=True)
+    torch.cuda.synchronize()
+    for job, fr in zip(jobs, outs):
+        g = to_numpy(fr)
+        o = orc.render(job)
+        cam = job["camera"]
+        nd = neighbour_flags(o["status"].reshape(cam["height"], cam["width"])).ravel()
+        st = compare(orc, job, g, o, nd)
+        assert_parity(st)
+
+
+def test_batch_speedup_over_one_by_one(frt, batch_jobs):
+    """Reports the throughput gain of one batched launch (and its graph
+    replay) over the same 64 renders launched one by one."""
+    frames = [frt.alloc_frame(j, "cuda") for j in batch_jobs]
+    ws = frt.alloc_workspace(len(batch_jobs), "cuda")
+    ws1 = frt.alloc_workspace(1, "cuda")
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        e.synchronize()
+        return s.elapsed_time(e) / reps
+
+    t_single = timed(lambda: [frt.render(j, "cuda", out=f, workspace=ws1) for j, f in zip(batch_jobs, frames)])
+    t_batch = timed(lambda: frt.render_batch(batch_jobs, "cuda", outs=frames, workspace=ws))
+    t_graph = timed(lambda: frt.render_batch(batch_jobs, "cuda", outs=frames, workspace=ws, use_graph=True))
+    frt.graph_reset()
+    print("64 renders: one by one %.3f ms, batched %.3f ms (x%.2f), graph %.3f ms (x%.2f)"
+          % (t_single, t_batch, t_single / t_batch, t_graph, t_single / t_graph))
+    assert t_batch < t_single
