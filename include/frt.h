@@ -147,9 +147,10 @@ typedef struct {
     frt_frame out;
 } frt_job;
 
-/* Device workspace needed by a call over n_jobs renders (job table and ray
- * queue counters).  Any device allocation of at least this many bytes,
- * 256-byte aligned, serves.                                                 */
+/* Device workspace needed by a call over n_jobs renders (work-queue
+ * counters, the job table and the adjoint's table of upstream-gradient
+ * pointers).  Any device allocation of at least this many bytes, 256-byte
+ * aligned, serves.                                                          */
 size_t frt_workspace_bytes(int32_t n_jobs);
 
 /* Render one view (the per-pixel path of Listings 2-5 and 7).
@@ -171,25 +172,38 @@ frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_
 frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace, size_t ws_bytes,
                             int32_t use_graph, void* stream);
 
-/* Adjoint of a batch render by implicit differentiation at the hit points:
- * for a refined hit, d t* / d theta = -(dd/dtheta) / (grad d . dir - eps_rel);
- * normal and colour follow by the chain rule through the normal taps, whose
- * orbit tangents are recomputed (nothing from the forward orbit is stored).
- * Cut-face hits use t* = (d - n_hat.o)/(n_hat.dir) and normal n_hat.
- * Exhausted and unrefined hits, misses and the shadow visibility contribute
- * nothing.
- * jobs: the forward jobs with out.depth and out.status from the forward
- *       call (other out pointers unused);
- * g_colour: host array of n_jobs device pointers, each float[3][P]
- *       (required); g_depth (float[P]) and g_normal (float[3][P]) host
- *       arrays may be NULL, as may any of their entries;
- * grad_c [n_jobs][4], grad_power [n_jobs], grad_plane [n_jobs][2][4] (raw
- *       n xyz, d): device float outputs, overwritten (zeroed, then
- *       accumulated with atomics, so the last bits vary run to run).
- * workspace: frt_workspace_bytes(n_jobs) bytes.                            */
+/* Adjoint of a batch render (the gradient the renderer is differentiated
+ * for, by implicit differentiation at the hit points; Sec. 2 gives the
+ * orbit-derivative estimate d whose root the depth is):
+ * for a refined hit, t* solves d(o + t dir) = eps_abs + eps_rel t, so
+ *   d t* / d theta = -(dd/dtheta) / (grad d . dir - eps_rel);
+ * normal (Eq. 5 / Listing 5 taps) and colour follow by the chain rule
+ * through the taps, whose orbit tangents are recomputed (nothing from the
+ * forward orbit is stored).  Cut-face hits use t* = (d - n_hat.o)/(n_hat.dir)
+ * and normal n_hat, n_hat = n / |n|.  Exhausted and unrefined hits, misses
+ * and the shadow visibility contribute nothing.
+ * The result is, per job, the gradient of
+ *   sum_p g_colour . colour + g_depth depth + g_normal . normal
+ * with respect to theta = (c0..c3 | power | plane 0 raw n xyz, d |
+ * plane 1 raw n xyz, d); slots a job does not use come out zero.
+ * jobs: the forward jobs, with out.depth and out.status holding the forward
+ *       results (the other out pointers are not read);
+ * g_colour / g_depth / g_normal: host arrays of n_jobs device pointers to
+ *       float[3][P] / float[P] / float[3][P] upstream gradients; an array
+ *       or any entry may be NULL (zero);
+ * grad_pixel: host array of n_jobs device pointers to float[13][P], or NULL
+ *       (as may any entry): receives each pixel's contribution (zeros where
+ *       none), for checking against a per-pixel reference;
+ * grad_c [n_jobs][4], grad_power [n_jobs], grad_plane [n_jobs][2][4]:
+ *       device outputs, overwritten (zeroed by the call, then accumulated
+ *       with float atomics, so the last bits vary from run to run);
+ * workspace: frt_workspace_bytes(n_jobs) bytes, not shared with a call in
+ *       flight on another stream.
+ * Errors: as frt_render_batch (validation before any launch, no writes);
+ * FRT_EINVAL also for a null gradient output or a null depth / status.     */
 frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float* const* g_colour,
                                const float* const* g_depth, const float* const* g_normal,
-                               float* grad_c, float* grad_power, float* grad_plane,
+                               float* const* grad_pixel, float* grad_c, float* grad_power, float* grad_plane,
                                void* workspace, size_t ws_bytes, void* stream);
 
 /* Distance estimate (Sec. 2, Eq. 2-4) at n points, the same orbit code the

@@ -79,7 +79,7 @@ def lib():
         L.frt_render.restype = ctypes.c_int
         L.frt_render_batch.argtypes = [P(Job), i32, vp, sz, i32, vp]
         L.frt_render_batch.restype = ctypes.c_int
-        L.frt_render_backward.argtypes = [P(Job), i32, P(vp), P(vp), P(vp), vp, vp, vp, vp, sz, vp]
+        L.frt_render_backward.argtypes = [P(Job), i32, P(vp), P(vp), P(vp), P(vp), vp, vp, vp, vp, sz, vp]
         L.frt_render_backward.restype = ctypes.c_int
         L.frt_autotune_set.argtypes = [i32, i32, i32, i32, i32, i32]
         L.frt_autotune_set.restype = ctypes.c_int
@@ -147,6 +147,8 @@ def _device(device):
     d = torch.device(device)
     if d.type != "cuda":
         raise FrtError("the renderer runs on a GPU device, got %s" % d)
+    if d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
     return d
 
 
@@ -209,6 +211,54 @@ def render_batch(jobs, device="cuda", counters=False, use_graph=False, outs=None
     arr = (Job * len(jobs))(*[make_job(j, f) for j, f in zip(jobs, frames)])
     _check(L.frt_render_batch(arr, len(jobs), _ptr(ws), ws.numel(), int(bool(use_graph)), _stream(dev)))
     return frames
+
+
+def render_backward(jobs, frames, g_colour=None, g_depth=None, g_normal=None, device="cuda", workspace=None,
+                    grads=None, per_pixel=False):
+    """Adjoint of render_batch(jobs): per-job gradients of
+    sum(g_colour * colour) + sum(g_depth * depth) + sum(g_normal * normal)
+    with respect to the fractal parameters and the raw cut planes.
+
+    frames: the forward frames (depth and status are read); g_colour,
+    g_depth, g_normal: lists with one tensor (or None) per job, or None.
+    Returns (grad_c [n, 4], grad_power [n], grad_plane [n, 2, 4]) on the
+    device, asynchronously on the current stream; with per_pixel=True also
+    a list of per-pixel contributions [13, P] per job (slots as in grad:
+    c0-c3, power, plane 0 n xyz d, plane 1 n xyz d)."""
+    L = lib()
+    dev = _device(device)
+    n = len(jobs)
+    ws = workspace if workspace is not None else alloc_workspace(n, dev)
+    if grads is None:
+        grads = (torch.empty(n, 4, device=dev, dtype=torch.float32), torch.empty(n, device=dev, dtype=torch.float32),
+                 torch.empty(n, 2, 4, device=dev, dtype=torch.float32))
+    keep = []
+
+    def table(gs, channels):
+        if gs is None:
+            return None
+        arr = (ctypes.c_void_p * n)()
+        for k, (g, j) in enumerate(zip(gs, jobs)):
+            if g is None:
+                continue
+            P = int(j["camera"]["width"]) * int(j["camera"]["height"])
+            if g.numel() != channels * P or g.dtype != torch.float32 or g.device != dev:
+                raise FrtError("gradient of job %d must be float32 with %d elements on %s" % (k, channels * P, dev))
+            g = g.contiguous()
+            keep.append(g)
+            arr[k] = g.data_ptr()
+        return arr
+
+    tc, td, tn = table(g_colour, 3), table(g_depth, 1), table(g_normal, 3)
+    pix, tp = None, None
+    if per_pixel:
+        pix = [torch.empty(13, int(j["camera"]["width"]) * int(j["camera"]["height"]), device=dev,
+                           dtype=torch.float32) for j in jobs]
+        tp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in pix])
+    arr = (Job * n)(*[make_job(j, f) for j, f in zip(jobs, frames)])
+    _check(L.frt_render_backward(arr, n, tc, td, tn, tp, _ptr(grads[0]), _ptr(grads[1]), _ptr(grads[2]), _ptr(ws),
+                                 ws.numel(), _stream(dev)))
+    return (grads + (pix,)) if per_pixel else grads
 
 
 def distance(fractal, points, device="cuda"):

@@ -80,13 +80,9 @@ int device_cus() {
     return cached[dev];
 }
 
-bool make_cfg(const void* kernel, int variant, long long total_rays, LaunchCfg& cfg, std::string& why) {
-    Tune t;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        t = g_tune[variant];
-    }
-    // occupancy of (kernel, block) on this device, queried once
+// Resident workgroups per CU of (kernel, block) on the current device,
+// queried once per (kernel, block, device).
+bool occupancy(const void* kernel, int block, int& per_cu, std::string& why) {
     struct OccEntry {
         const void* kernel;
         int block;
@@ -97,21 +93,31 @@ bool make_cfg(const void* kernel, int variant, long long total_rays, LaunchCfg& 
     static std::vector<OccEntry> occ_cache;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    int per_cu = 0;
+    per_cu = 0;
     {
         std::lock_guard<std::mutex> lk(occ_mu);
         for (const OccEntry& o : occ_cache)
-            if (o.kernel == kernel && o.block == t.block && o.device == dev) per_cu = o.per_cu;
+            if (o.kernel == kernel && o.block == block && o.device == dev) per_cu = o.per_cu;
     }
-    if (per_cu == 0) {
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, t.block, 0);
-        if (e != hipSuccess || per_cu <= 0) {
-            why = std::string("occupancy query failed: ") + hipGetErrorString(e);
-            return false;
-        }
-        std::lock_guard<std::mutex> lk(occ_mu);
-        occ_cache.push_back(OccEntry{kernel, t.block, dev, per_cu});
+    if (per_cu > 0) return true;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
+    if (e != hipSuccess || per_cu <= 0) {
+        why = std::string("occupancy query failed: ") + hipGetErrorString(e);
+        return false;
     }
+    std::lock_guard<std::mutex> lk(occ_mu);
+    occ_cache.push_back(OccEntry{kernel, block, dev, per_cu});
+    return true;
+}
+
+bool make_cfg(const void* kernel, int variant, long long total_rays, LaunchCfg& cfg, std::string& why) {
+    Tune t;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        t = g_tune[variant];
+    }
+    int per_cu = 0;
+    if (!occupancy(kernel, t.block, per_cu, why)) return false;
     if (t.waves_per_simd > 0) {
         const int want = (t.waves_per_simd * 4 * 64) / t.block;   // 4 SIMDs per CU
         per_cu = std::max(1, std::min(per_cu, want));
@@ -218,9 +224,14 @@ void pack(const frt_camera* cam, const frt_fractal* fr, const frt_plane* planes,
         J.fwd[k] = float(f[k]);
         J.right[k] = float(r[k]);
         J.upv[k] = float(u[k]);
+        J.fwd_d[k] = f[k];
+        J.right_d[k] = r[k];
+        J.upv_d[k] = u[k];
     }
     J.sx = float(s * cam->width / cam->height);
     J.sy = float(s);
+    J.sx_d = s * cam->width / cam->height;
+    J.sy_d = s;
     J.inv_w2 = float(2.0 / cam->width);
     J.inv_h2 = float(2.0 / cam->height);
     J.width = cam->width;
@@ -310,9 +321,12 @@ std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;
 hipStream_t g_capture_stream = nullptr;
 
+// Copy header + job table (+ the adjoint's table, if given) into the
+// workspace through one pinned staging buffer.
 frt_status upload_table(const std::vector<JobDev>& jobs, const WorkspaceHeader& hdr, void* workspace,
-                        hipStream_t stream) {
-    const size_t bytes = sizeof(WorkspaceHeader) + jobs.size() * sizeof(JobDev);
+                        hipStream_t stream, const std::vector<frt::AdjointJob>* ajobs = nullptr) {
+    const size_t table = sizeof(WorkspaceHeader) + jobs.size() * sizeof(JobDev);
+    const size_t bytes = table + (ajobs ? ajobs->size() * sizeof(frt::AdjointJob) : 0);
     std::lock_guard<std::mutex> lk(g_stage_mu);
     hipError_t e;
     if (g_stage.pending) {
@@ -334,6 +348,7 @@ frt_status upload_table(const std::vector<JobDev>& jobs, const WorkspaceHeader& 
     }
     std::memcpy(g_stage.host, &hdr, sizeof(hdr));
     std::memcpy(static_cast<char*>(g_stage.host) + sizeof(hdr), jobs.data(), jobs.size() * sizeof(JobDev));
+    if (ajobs) std::memcpy(static_cast<char*>(g_stage.host) + table, ajobs->data(), bytes - table);
     e = hipMemcpyAsync(workspace, g_stage.host, bytes, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
     e = hipEventRecord(g_stage.done, stream);
@@ -356,7 +371,8 @@ extern "C" {
 
 size_t frt_workspace_bytes(int32_t n_jobs) {
     if (n_jobs < 1) n_jobs = 1;
-    return size_t(round_up(int64_t(sizeof(WorkspaceHeader)) + int64_t(n_jobs) * int64_t(sizeof(JobDev)), 256));
+    const int64_t per_job = int64_t(sizeof(JobDev)) + int64_t(sizeof(frt::AdjointJob));
+    return size_t(round_up(int64_t(sizeof(WorkspaceHeader)) + int64_t(n_jobs) * per_job, 256));
 }
 
 frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_plane* planes, int32_t n_planes,
@@ -503,13 +519,66 @@ frt_status frt_math_eval(int32_t func, const float* x, const float* y, float* ou
 }
 
 frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float* const* g_colour,
-                               const float* const* g_depth, const float* const* g_normal, float* grad_c,
+                               const float* const* g_depth, const float* const* g_normal,
+                               float* const* grad_pixel, float* grad_c,
                                float* grad_power, float* grad_plane, void* workspace, size_t ws_bytes,
                                void* stream) {
-    (void)jobs; (void)n_jobs; (void)g_colour; (void)g_depth; (void)g_normal; (void)grad_c; (void)grad_power;
-    (void)grad_plane; (void)workspace; (void)ws_bytes; (void)stream;
     g_last_error.clear();
-    return fail(FRT_EUNSUPPORTED, "adjoint not built");
+    if (!jobs || n_jobs < 1) return fail(FRT_EINVAL, "jobs is null or n_jobs < 1");
+    if (!grad_c || !grad_power || !grad_plane) return fail(FRT_EINVAL, "null gradient output");
+    frt_status s = check_workspace(workspace, ws_bytes, n_jobs);
+    if (s != FRT_OK) return s;
+    std::vector<JobDev> table(static_cast<size_t>(n_jobs));
+    std::vector<frt::AdjointJob> adj(static_cast<size_t>(n_jobs));
+    int64_t begin = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        std::string why;
+        const frt_job& jb = jobs[i];
+        if (!validate(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, &jb.out, false, why))
+            return fail(FRT_EINVAL, "job " + std::to_string(i) + ": " + why);
+        if (!jb.out.depth || !jb.out.status)
+            return fail(FRT_EINVAL, "job " + std::to_string(i) + ": null depth or status plane");
+        pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, begin, table[size_t(i)]);
+        begin += table[size_t(i)].ray_count;
+        frt::AdjointJob& a = adj[size_t(i)];
+        a.g_colour = g_colour ? g_colour[i] : nullptr;
+        a.g_depth = g_depth ? g_depth[i] : nullptr;
+        a.g_normal = g_normal ? g_normal[i] : nullptr;
+        a.g_pixel = grad_pixel ? grad_pixel[i] : nullptr;
+        for (int k = 0; k < 2; ++k)
+            for (int e = 0; e < 3; ++e) a.raw_n[k][e] = k < jb.n_planes ? jb.planes[k].n[e] : 0.0f;
+    }
+    WorkspaceHeader hdr;
+    std::memset(&hdr, 0, sizeof(hdr));
+    hdr.total_rays = static_cast<unsigned long long>(begin);
+    hdr.n_jobs = n_jobs;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    s = upload_table(table, hdr, workspace, st, &adj);
+    if (s != FRT_OK) return s;
+    char* base = static_cast<char*>(workspace);
+    frt::AdjointArgs a;
+    a.jobs = reinterpret_cast<const JobDev*>(base + sizeof(WorkspaceHeader));
+    a.ajobs = reinterpret_cast<const frt::AdjointJob*>(base + sizeof(WorkspaceHeader) + size_t(n_jobs) * sizeof(JobDev));
+    a.grad_c = grad_c;
+    a.grad_power = grad_power;
+    a.grad_plane = grad_plane;
+    a.n_jobs = n_jobs;
+    std::string why;
+    for (int kind = 0; kind < 2; ++kind) {
+        long long rays = 0;
+        for (const JobDev& J : table)
+            if (J.kind == kind) rays += J.ray_count;
+        a.grid[kind] = 0;
+        if (rays == 0) continue;
+        int per_cu = 0;
+        if (!occupancy(frt::adjoint_kernel_symbol(kind), 256, per_cu, why)) return fail(FRT_EHIP, why);
+        const long long wgs_needed = (rays / 64 + 3) / 4;
+        a.grid[kind] = static_cast<int>(
+            std::max<long long>(1, std::min<long long>(static_cast<long long>(per_cu) * device_cus(), wgs_needed)));
+    }
+    hipError_t e = frt::launch_adjoint(a, static_cast<WorkspaceHeader*>(workspace), st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    return FRT_OK;
 }
 
 frt_status frt_autotune_set(int32_t kernel_variant, int32_t block, int32_t chunk, int32_t waves_per_simd,

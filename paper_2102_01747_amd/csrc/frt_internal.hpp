@@ -33,14 +33,20 @@ hipError_t launch_distance(int variant, const OrbitParams& P, const float* pts, 
                            hipStream_t stream);
 hipError_t launch_math(int func, const float* x, const float* y, float* out, long long n, hipStream_t stream);
 
-// Adjoint kernel over the hit pixels of a batch (device job table).
+// Adjoint over the hit pixels of a batch (frt_adjoint.hip): zeroes the
+// gradient outputs and the tile counters, then one persistent launch per
+// fractal kind present (grid[kind] workgroups of 256 threads, 0 = none)
+// drains the batch's 64-ray tiles.
 struct AdjointArgs {
-    const JobDev* jobs;        // device table
+    const JobDev* jobs;        // device job table
     const AdjointJob* ajobs;   // device table of upstream-gradient pointers
-    float* grad;               // [n_jobs][kGradSlots]
+    float* grad_c;             // [n_jobs][4]
+    float* grad_power;         // [n_jobs]
+    float* grad_plane;         // [n_jobs][2][4]
     int n_jobs;
+    int grid[2];
 };
-hipError_t launch_adjoint(const LaunchCfg& cfg, const AdjointArgs& a, WorkspaceHeader* hdr, hipStream_t stream);
-const void* adjoint_kernel_symbol();
+hipError_t launch_adjoint(const AdjointArgs& a, WorkspaceHeader* hdr, hipStream_t stream);
+const void* adjoint_kernel_symbol(int kind);
 
 }  // namespace frt

@@ -66,17 +66,23 @@ struct alignas(16) JobDev {
     // position in the batch's ray index space (multiples of 64)
     int64_t ray_begin;
     int64_t ray_count;
+    // camera basis and screen scales in FP64 (the adjoint's rays)
+    double fwd_d[3];
+    double right_d[3];
+    double upv_d[3];
+    double sx_d, sy_d;
 };
 
 // Gradient slots per job: c0..c3, power, plane 0 (raw n xyz, d), plane 1.
 constexpr int kGradSlots = 13;
 
-// Upstream gradients of one job for the adjoint (device pointers, the last
-// two may be null).
+// Upstream gradients of one job for the adjoint (device pointers; any may
+// be null).
 struct AdjointJob {
     const float* g_colour;   // [3][P]
     const float* g_depth;    // [P]
     const float* g_normal;   // [3][P]
+    float* g_pixel;          // [kGradSlots][P] per-pixel contributions (optional)
     float raw_n[2][3];       // raw plane normals (the job holds unit ones)
 };
 
@@ -87,12 +93,14 @@ struct AdjointJob {
 // segments: 5.7 ms vs 4.7 ms per step), so one segment is used.
 constexpr int kQueues = 1;
 
-// Workspace layout: a 1 KiB header, then the job table.
+// Workspace layout: a 1 KiB header, the job table, then the table of
+// upstream-gradient pointers (AdjointJob, read by the adjoint only).
 struct alignas(256) WorkspaceHeader {
     unsigned long long queue[2][kQueues];   // claimed rays per segment: primary march, shadow march
+    unsigned long long adj_queue[2];        // 64-ray tiles claimed by the adjoint kernels (per kind)
     unsigned long long total_rays;
     int32_t n_jobs;
-    int32_t pad[(1024 - 16 * kQueues - 12) / 4];
+    int32_t pad[(1024 - 16 * kQueues - 28) / 4];
 };
 static_assert(sizeof(WorkspaceHeader) == 1024, "workspace header must be 1 KiB");
 

@@ -100,6 +100,68 @@ def normal_ill_conditioned(orc, fr, mc, pts, dirs, eps, seeds=4, tol=2e-4, margi
     return ill
 
 
+def boundary_set(g, o, neigh_diff, dirs):
+    """The boundary set B of the module docstring (per compared pixel)."""
+    gs, os_ = g["status"].astype(np.int64), o["status"].astype(np.int64)
+    gc, oc = gs & CLS_MASK, os_ & CLS_MASK
+    B = neigh_diff.copy()
+    B |= (gc == 4) | (oc == 4) | ((os_ & 32) != 0)
+    if "counters" in g:
+        B |= (g["counters"][3].astype(np.int64) != o["hit_iters"])
+        B |= (g["counters"][0].astype(np.int64) != o["steps"])
+    B |= (oc >= 2) & (np.abs(np.einsum("ij,ij->i", o["normal"].T, dirs)) < 0.05)
+    return B
+
+
+def adjoint_mask(orc, job, g, o):
+    """Pixels (whole image) where the adjoint's per-pixel contribution is
+    compared: both sides report the same smooth hit class (refined surface
+    hit or cut face), the pixel is outside B, and a surface hit's normal is
+    well conditioned at float32 resolution.  Elsewhere the two sides may
+    legitimately differentiate different branches."""
+    cam, mc, fr = job["camera"], job["march"], job["fractal"]
+    H, W = cam["height"], cam["width"]
+    pixels = np.arange(H * W)
+    gs, os_ = g["status"].astype(np.int64), o["status"].astype(np.int64)
+    gc, oc = gs & CLS_MASK, os_ & CLS_MASK
+    _, dirs = orc.camera_rays(cam, pixels)
+    B = boundary_set(g, o, neighbour_flags(o["status"].reshape(H, W)).ravel(), dirs)
+    smooth = ((gs & 16) == 0) & ((os_ & (16 | 32)) == 0) & np.isin(gc, (2, 3)) & (gc == oc)
+    shade_same = (gs & 8) == (os_ & 8)
+    M = smooth & shade_same & ~B
+    surf = np.nonzero(M & (gc == 2))[0]
+    if surf.size:
+        orig, d = orc.camera_rays(cam, surf)
+        ts = g["depth"][surf].astype(np.float64)
+        pts = orig + ts[:, None] * d
+        eps = mc["eps_abs"] + mc["eps_rel"] * ts
+        M[surf[normal_ill_conditioned(orc, fr, mc, pts, d, eps)]] = False
+    return M
+
+
+def jacobian_sensitivity(orc, job, pix, J0, slots, shift=2e-7):
+    """Per pixel: the largest relative change of the oracle's Jacobian
+    (columns `slots`, relative to 1e-3 + |J|) when the camera is shifted by
+    `shift` along each axis.  The GPU forms its hit point in float32 (depth
+    and ray direction rounded at ~1e-7), and on fine fractal detail the
+    derivatives of the normal change measurably over that distance; where
+    this sensitivity is large the two sides differentiate at legitimately
+    different points."""
+    import copy
+    sens = np.zeros(pix.size)
+    ref = J0[:, :, slots]
+    for ax in range(3):
+        for sg in (-1.0, 1.0):
+            jb = copy.deepcopy(job)
+            eye = list(jb["camera"]["eye"])
+            eye[ax] = float(np.float64(eye[ax]) + sg * shift)
+            jb["camera"]["eye"] = eye
+            J1, _ = orc.pixel_jacobian(jb, pix)
+            rel = np.abs(J1[:, :, slots] - ref) / (1e-3 + np.abs(ref))
+            sens = np.maximum(sens, rel.max(axis=(1, 2)))
+    return sens
+
+
 def compare(orc, job, g, o, neigh_diff, pixels=None):
     """g: GPU frame (numpy, restricted to `pixels` if given); o: oracle render
     of the same pixels; neigh_diff: neighbour flags of those pixels."""
@@ -113,13 +175,8 @@ def compare(orc, job, g, o, neigh_diff, pixels=None):
     stats = {"pixels": int(n), "hit_agree": float(np.mean(ghit == ohit)), "gpu_hits": int(ghit.sum()),
              "oracle_hits": int(ohit.sum())}
     orig, dirs = orc.camera_rays(cam, pixels)
-    B = neigh_diff.copy()
-    B |= (gc == 4) | (oc == 4) | ((os_ & 32) != 0)
-    if "counters" in g:
-        B |= (g["counters"][3].astype(np.int64) != o["hit_iters"])
-        B |= (g["counters"][0].astype(np.int64) != o["steps"])
+    B = boundary_set(g, o, neigh_diff, dirs)
     on = o["normal"].T
-    B |= ohit & (np.abs(np.einsum("ij,ij->i", on, dirs)) < 0.05)
     both = ghit & ohit & ~B
     stats["boundary_frac"] = float(B.mean())
     stats["compared"] = int(both.sum())

@@ -1,0 +1,283 @@
+"""Adjoint of the renderer on the GPU (implicit differentiation at the hit
+points) against the FP64 oracle.
+
+* Per pixel: the kernel's contribution of every pixel (its optional
+  per-pixel output) against the oracle's dual-number Jacobian contracted
+  with the same seeded cotangent, on the pixels where both sides
+  differentiate the same smooth branch (parity.adjoint_mask).
+* Per job: the kernel's summed gradient against FP64 central finite
+  differences of the oracle render, over a fixed mask of pixels that are
+  stable under every perturbation (gradcheck); relative error per parameter
+  group below 1e-4 (the target is 1e-3).
+* Batch vs single calls, the autograd Function, error handling, and the
+  cost of the backward pass against the forward pass.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gradcheck import finite_differences
+from parity import adjoint_mask, jacobian_sensitivity, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = {"c": [0, 1, 2, 3], "n": [4], "plane0": [5, 6, 7, 8], "plane1": [9, 10, 11, 12]}
+
+
+@pytest.fixture(scope="module")
+def frt():
+    import paper_2102_01747_amd as m
+    m.lib()
+    return m
+
+
+CASES = {
+    "julia_cut": (lambda: W.julia_view(width=64, height=64, planes=[W.plane([0.3, 0.2, 1.0], 0.05)]),
+                  [0, 1, 2, 3, 5, 6, 7, 8]),
+    # surface hits beside a cut face (c and plane in one view)
+    "julia_side_cut": (lambda: W.julia_view(width=64, height=64, planes=[W.plane([1.0, 0.0, 0.3], 0.2)]),
+                       [0, 1, 2, 3, 5, 6, 7, 8]),
+    # both planes are entry planes for some pixels, plus surface hits
+    "julia_two_planes_central": (lambda: W.julia_view(width=64, height=64, normal_mode="central",
+                                                      planes=[W.plane([1.0, 0.2, 0.3], 0.1),
+                                                              W.plane([-0.4, 1.0, 0.3], 0.3)]),
+                                 [0, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12]),
+    "julia_no_plane": (lambda: W.julia_view(width=64, height=64), [0, 1, 2, 3]),
+    "bulb8_cut_shadow": (lambda: W.bulb_view(0.7, 0.2, width=64, height=64, shadow=True,
+                                             planes=[W.plane([0.2, 1.0, 0.1], 0.1)]), [4, 5, 6, 7, 8]),
+    "bulb8_two_planes_shadow": (lambda: W.bulb_view(0.7, 0.2, width=64, height=64, shadow=True,
+                                                    planes=[W.plane([0.2, 1.0, 0.1], 0.1),
+                                                            W.plane([1.0, 0.0, 0.2], 0.2)]),
+                                [4, 5, 6, 7, 8, 9, 10, 11, 12]),
+    "bulb_real_power": (lambda: W.bulb_view(2.1, -0.3, width=56, height=56, power=6.37, shadow=False), [4]),
+    "bulb8_tetra": (lambda: W.bulb_view(4.0, 0.4, width=56, height=56, shadow=False, normal_mode="tetra"), [4]),
+}
+
+
+def _cotangent(job, seed, mask=None):
+    cam = job["camera"]
+    P = cam["width"] * cam["height"]
+    rng = np.random.default_rng(seed)
+    gc = rng.normal(size=(3, P)).astype(np.float32)
+    gd = rng.normal(size=P).astype(np.float32)
+    gn = rng.normal(size=(3, P)).astype(np.float32)
+    if mask is not None:
+        gc[:, ~mask] = 0.0
+        gd[~mask] = 0.0
+        gn[:, ~mask] = 0.0
+    return gc, gd, gn
+
+
+def _contract(J, gc, gd, gn, idx):
+    """Oracle per-pixel contribution [n, 13] = w . J for pixels idx."""
+    w = np.concatenate([gd[None, idx], gn[:, idx], gc[:, idx]], 0).astype(np.float64)   # [7, n]
+    return np.einsum("rn,nrs->ns", w, J), np.einsum("rn,nrs->ns", np.abs(w), np.abs(J))
+
+
+def _gpu_backward(frt, job, fr, gc, gd, gn, per_pixel=False):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = frt.render_backward([job], [fr], [t(gc)], [t(gd)], [t(gn)], "cuda", per_pixel=per_pixel)
+    torch.cuda.synchronize()
+    g = np.concatenate([out[0].cpu().numpy().ravel(), out[1].cpu().numpy().ravel(), out[2].cpu().numpy().ravel()])
+    if per_pixel:
+        return g, out[3][0].cpu().numpy()
+    return g
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_adjoint_per_pixel_matches_oracle_jacobian(frt, orc, case):
+    """Every pixel's contribution against the oracle Jacobian contracted with
+    the same cotangent, on the adjoint mask.  Per pixel the bound is 1e-4
+    (relative to the contribution's scale) plus twice the oracle's own
+    change when the hit point moves by float32 resolution (the kernel
+    polishes the float32 hit point in FP64, but a few pixels sit where the
+    two roots differ); the median error must stay below 1e-6."""
+    make, slots = CASES[case]
+    jb = make()
+    fr = frt.render(jb, "cuda", counters=True)
+    torch.cuda.synchronize()
+    g = to_numpy(fr)
+    o = orc.render(jb)
+    M = adjoint_mask(orc, jb, g, o)
+    idx = np.nonzero(M)[0]
+    assert idx.size > 300, idx.size
+    J, _ = orc.pixel_jacobian(jb, idx)
+    sens = jacobian_sensitivity(orc, jb, idx, J, slots)
+    gc, gd, gn = _cotangent(jb, 11, M)
+    total, pix = _gpu_backward(frt, jb, fr, gc, gd, gn, per_pixel=True)
+    ref, mag = _contract(J, gc, gd, gn, idx)
+    gpu = pix[:, idx].T.astype(np.float64)
+    err = (np.abs(gpu - ref) / (1e-3 + mag))[:, slots]
+    within = err <= 1e-4 + 2.0 * sens[:, None]
+    print("%s: %d pixels (%.3f of image); per-pixel err / scale p50 %.2e p90 %.2e max %.2e; "
+          "sensitivity p50 %.2e, %.3f above 1e-3; within bound %.4f"
+          % (case, idx.size, M.mean(), np.median(err), np.quantile(err, 0.9), err.max(), np.median(sens),
+             np.mean(sens > 1e-3), within.mean()))
+    assert np.median(err) < 1e-6
+    assert within.mean() >= 0.995, within.mean()
+    # pixels outside the mask have zero cotangent and contribute exactly zero
+    assert np.all(pix[:, ~M] == 0.0)
+    # the atomically summed gradient is the sum of the per-pixel contributions
+    sums = pix.astype(np.float64).sum(1)
+    assert np.allclose(total, sums, rtol=1e-4, atol=1e-4 * np.abs(pix).sum(1).max())
+    # slots the job does not use stay zero
+    unused = [s for s in range(13) if s not in slots]
+    assert np.all(total[unused] == 0.0)
+
+
+# parameter offsets of the target renders of the loss (slots as in GROUPS)
+TARGET_STEP = np.array([0.01, -0.01, 0.005, 0.0, 0.05, 0.02, -0.01, 0.01, 0.01, -0.01, 0.02, 0.0, -0.01])
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_adjoint_matches_fp64_finite_differences(frt, orc, case):
+    """Gradient of the loss of the differentiable set -- squared colour,
+    depth and normal error to a render at offset parameters -- over a fixed
+    mask of stable pixels, against FP64 central differences of the oracle
+    render of the same masked loss (cotangent fixed at the GPU forward
+    values); relative error per parameter group below 1e-4 (the target is
+    1e-3)."""
+    from paper_2102_01747_amd.autograd import job_params, job_with_params
+
+    make, slots = CASES[case]
+    jb = make()
+    fr = frt.render(jb, "cuda", counters=True)
+    tj = job_with_params(jb, job_params(jb) + TARGET_STEP)
+    tfr = frt.render(tj, "cuda")
+    torch.cuda.synchronize()
+    g, t = to_numpy(fr), to_numpy(tfr)
+    o = orc.render(jb)
+    M = adjoint_mask(orc, jb, g, o)
+    idx = np.nonzero(M)[0]
+    J, taps = orc.pixel_jacobian(jb, idx)
+    scale = 1.0 + np.abs(J.transpose(1, 0, 2))
+    fd, stable = finite_differences(orc, jb, idx, slots, o["status"][idx], taps, scale)
+    keep = np.ones(idx.size, bool)
+    for s in slots:
+        keep &= stable[s]
+    assert keep.mean() > 0.95, keep.mean()
+    M2 = np.zeros_like(M)
+    M2[idx[keep]] = True
+    both = M2 & ((t["status"] & 7) >= 2) & ((t["status"] & 7) != 4)
+    gc = np.where(M2, 2.0 * (g["colour"] - t["colour"]), 0.0).astype(np.float32)
+    gd = np.where(both, 0.5 * 2.0 * (g["depth"] - t["depth"]), 0.0).astype(np.float32)
+    gn = np.where(both, 0.5 * 2.0 * (g["normal"] - t["normal"]), 0.0).astype(np.float32)
+    gpu = _gpu_backward(frt, jb, fr, gc, gd, gn).astype(np.float64)
+    w = np.concatenate([gd[None, idx], gn[:, idx], gc[:, idx]], 0).astype(np.float64)   # [7, n]
+    gfd = np.zeros(13)
+    for s in slots:
+        gfd[s] = np.sum(w * fd[s])
+    report = {}
+    for name, grp in GROUPS.items():
+        grp = [s for s in grp if s in slots]
+        if not grp:
+            continue
+        ref = np.linalg.norm(gfd[grp])
+        if ref == 0.0:   # no stable pixel depends on this group (e.g. a plane that cuts nothing in view)
+            assert np.all(gpu[grp] == 0.0), (name, gpu[grp])
+            continue
+        report[name] = np.linalg.norm(gpu[grp] - gfd[grp]) / ref
+    print("%s: %d stable pixels; rel err vs FP64 FD %s" % (case, keep.sum(),
+                                                          {k: "%.2e" % v for k, v in report.items()}))
+    expected = {name for name, grp in GROUPS.items() if set(grp) & set(slots)}
+    if case == "julia_cut":
+        expected.discard("c")   # the cut face covers the view; its surface pixels all border it
+    assert set(report) == expected, (set(report), expected)
+    for name, rel in report.items():
+        assert rel < 1e-4, (name, rel, report)
+
+
+def test_batch_adjoint_equals_single_calls(frt):
+    jobs = [W.julia_view(width=72, height=40, planes=[W.plane([0.3, 0.2, 1.0], 0.05)]),
+            W.bulb_view(0.7, 0.2, width=64, height=48, shadow=True, planes=[W.plane([0.2, 1.0, 0.1], 0.1)]),
+            W.julia_view(c=(-0.4, 0.5, 0.1, 0.3), width=33, height=65),
+            W.bulb_view(2.1, -0.3, width=40, height=40, power=6.37, shadow=False),
+            W.julia_view(width=128, height=96, normal_mode="central", planes=[W.plane([-1.0, 0.4, 0.2], 0.3)])]
+    frames = frt.render_batch(jobs, "cuda")
+    cots = [_cotangent(j, 20 + k) for k, j in enumerate(jobs)]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    gb = frt.render_backward(jobs, frames, [t(c[0]) for c in cots], [t(c[1]) for c in cots],
+                             [t(c[2]) for c in cots], "cuda")
+    torch.cuda.synchronize()
+    batch = np.concatenate([gb[0].cpu().numpy(), gb[1].cpu().numpy()[:, None],
+                            gb[2].cpu().numpy().reshape(len(jobs), 8)], 1)
+    for k, (j, f, c) in enumerate(zip(jobs, frames, cots)):
+        single = _gpu_backward(frt, j, f, *c)
+        assert np.allclose(batch[k], single, rtol=1e-4, atol=1e-5 * np.abs(single).max()), (k, batch[k], single)
+
+
+def test_autograd_function_matches_direct_call(frt):
+    from paper_2102_01747_amd.autograd import job_params, render_diff
+
+    jobs = [W.julia_view(width=64, height=64, planes=[W.plane([0.3, 0.2, 1.0], 0.05)]),
+            W.bulb_view(0.7, 0.2, width=64, height=64, shadow=False, planes=[W.plane([0.2, 1.0, 0.1], 0.1)])]
+    theta = torch.tensor(np.stack([job_params(j) for j in jobs]), dtype=torch.float64, requires_grad=True)
+    target_theta = theta.detach().clone()
+    target_theta[0, :4] += 0.01
+    target_theta[1, 4] += 0.05
+    with torch.no_grad():
+        tgt = render_diff(jobs, target_theta)
+    outs = render_diff(jobs, theta)
+    loss = sum(((o["colour"] - t["colour"]) ** 2).sum() + 0.1 * o["depth"].sum() for o, t in zip(outs, tgt))
+    loss.backward()
+    assert theta.grad is not None and torch.isfinite(theta.grad).all()
+    # the same gradient through the C ABI directly
+    from paper_2102_01747_amd.autograd import job_with_params
+    rjobs = [job_with_params(j, r) for j, r in zip(jobs, theta.detach().numpy())]
+    fr2 = frt.render_batch(rjobs, "cuda")
+    gc = [(2 * (o["colour"] - t["colour"])).detach().reshape(-1) for o, t in zip(outs, tgt)]
+    gd = [torch.full_like(o["depth"].reshape(-1), 0.1) for o in outs]
+    g = frt.render_backward(rjobs, fr2, gc, gd, None, "cuda")
+    torch.cuda.synchronize()
+    direct = torch.cat([g[0], g[1].view(-1, 1), g[2].view(-1, 8)], 1).cpu().double()
+    assert torch.allclose(theta.grad, direct, rtol=1e-4, atol=1e-6 * float(direct.abs().max())), (theta.grad, direct)
+    assert float(theta.grad[0, :4].abs().sum()) > 0 and float(theta.grad[1, 4].abs()) > 0
+    assert float(theta.grad[0, 5:9].abs().sum()) > 0   # plane 0 of the Julia job
+
+
+def test_backward_rejects_bad_arguments(frt):
+    jb = W.julia_view(width=16, height=16)
+    fr = frt.render(jb, "cuda")
+    bad = torch.zeros(5, device="cuda")
+    with pytest.raises(frt.FrtError):
+        frt.render_backward([jb], [fr], [bad], None, None, "cuda")
+    jb2 = W.julia_view(width=16, height=16)
+    jb2["fractal"]["max_iter"] = 0
+    with pytest.raises(frt.FrtError):
+        frt.render_backward([jb2], [fr], None, None, None, "cuda")
+    # no cotangent at all: zero gradient
+    g = frt.render_backward([jb], [fr], None, None, None, "cuda")
+    torch.cuda.synchronize()
+    assert float(g[0].abs().sum() + g[1].abs().sum() + g[2].abs().sum()) == 0.0
+
+
+def test_backward_cost_against_forward(frt):
+    """Differentiable set: 8 Julia + 8 Mandelbulb renders of 512x512 with a
+    cut plane; the cotangent is that of the squared colour error to the
+    target renders.  Backward (adjoint launch) over forward (batch render)
+    time, both timed with events on the current stream."""
+    jobs, targets = W.diff_set()
+    frames = frt.render_batch(jobs, "cuda")
+    tframes = frt.render_batch(targets, "cuda")
+    torch.cuda.synchronize()
+    gc = [2.0 * (f["colour"] - t["colour"]) for f, t in zip(frames, tframes)]
+    ws_f = frt.alloc_workspace(len(jobs), "cuda")
+    ws_b = frt.alloc_workspace(len(jobs), "cuda")
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        e.synchronize()
+        return s.elapsed_time(e) / reps
+
+    t_f = timed(lambda: frt.render_batch(jobs, "cuda", outs=frames, workspace=ws_f))
+    t_b = timed(lambda: frt.render_backward(jobs, frames, gc, None, None, "cuda", workspace=ws_b))
+    print("differentiable set (16 x 512^2): forward %.3f ms, backward %.3f ms (x%.2f), %.0f gradients/s"
+          % (t_f, t_b, t_b / t_f, len(jobs) / ((t_f + t_b) * 1e-3)))
+    assert t_b <= 3.0 * t_f
