@@ -7,13 +7,15 @@ hit), rendered in one batch (primary-march, normal and shadow-march kernels,
 each one launch over all eight views).  Inputs (camera and fractal
 parameters) and output planes are resident in HBM before timing starts.
 
-Before timing, the launch configuration is autotuned on this workload
-(untimed; --no-tune keeps the library defaults).  Prints one JSON line with
+The launch configuration is the one the autotuner recorded for this kernel
+variant (paper_2102_01747_amd/tuned.json; --tune searches again, untimed).  Prints one JSON line with
 the throughput, the roofline of the dominant kernel (algorithmic FP32 FLOP
 per launch over its duration measured with HIP events on its stream, against
-the 157.3 TFLOP/s FP32 vector peak), the same figures for every stage, and
-the FP64 CPU oracle timed on a bounded pixel sample of the same workload on
-the host cores.
+the 157.3 TFLOP/s FP32 vector peak), the same figures for every stage, the
+adjoint leg (gradients per second of the differentiable set, backward over
+forward cost, and the finite-difference gradient it replaces), and the FP64
+CPU oracle timed on a bounded pixel sample of the same workload on the host
+cores.
 """
 import argparse
 import json
@@ -38,6 +40,21 @@ FLOP_PER_EVAL = 16.0
 STAGES = ("primary_march", "normals", "shadow_march")
 
 
+# sources of the forward kernels; the recorded HBM traffic is used only while
+# they are unchanged since the counters were taken
+KERNEL_SOURCES = ("frt_trace.hip", "frt_fractal.hpp", "frt_math.hpp", "frt_ray.hpp", "frt_job.hpp")
+
+
+def kernel_sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2102_01747_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def stage_flop(kind, counters):
     """Algorithmic FLOP of each stage from the per-pixel counter planes
     (1/2 primary evaluations/bodies, 4/5 normal taps, 6/7 shadow rays)."""
@@ -45,20 +62,99 @@ def stage_flop(kind, counters):
     return [FLOP_PER_BODY[kind] * c[bo].sum() + FLOP_PER_EVAL * c[ev].sum() for ev, bo in ((1, 2), (4, 5), (6, 7))]
 
 
-def cpu_baseline(jobs, stride):
+def cpu_baseline(jobs, target_s=20.0):
+    """The FP64 oracle on the host cores over a stratified pixel sample of
+    the same views: a stride-16 probe sets the rate, then the densest stride
+    expected to finish in about `target_s` seconds is timed."""
     import workloads as W
     from oracle import oracle as orc
 
-    n = 0
-    t0 = time.perf_counter()
-    for v, job in enumerate(jobs):
-        pix = W.stratified_pixels(job["camera"]["width"], job["camera"]["height"], stride, seed=100 + v)
-        orc.render(job, pixels=pix)
-        n += pix.size
-    dt = time.perf_counter() - t0
+    def run(stride):
+        n = 0
+        t0 = time.perf_counter()
+        for v, job in enumerate(jobs):
+            pix = W.stratified_pixels(job["camera"]["width"], job["camera"]["height"], stride, seed=100 + v)
+            orc.render(job, pixels=pix)
+            n += pix.size
+        return n, time.perf_counter() - t0
+
+    n, dt = run(16)
+    rate = n / dt
+    total = sum(j["camera"]["width"] * j["camera"]["height"] for j in jobs)
+    stride = 16
+    for s in (1, 2, 3, 4, 6, 8, 12):
+        if total / (s * s) / rate <= target_s:
+            stride = s
+            break
+    if stride != 16:
+        n, dt = run(stride)
     return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": orc.max_threads(), "kind": "oracle",
-            "sample": "FP64 oracle on one pixel per %dx%d cell of each of the %d views (%d rays, %.1f s), "
-                      "same shading and shadow rays" % (stride, stride, len(jobs), n, dt)}
+            "sample": "FP64 oracle (OpenMP over rays) on one pixel per %dx%d cell of each of the %d views "
+                      "(%d of %d rays, %.1f s), same normals and shadow rays" % (stride, stride, len(jobs), n, total, dt)}
+
+
+def adjoint_leg(frt, dev, reps):
+    """Differentiable set: 8 Julia + 8 Mandelbulb renders of 512x512 with a
+    cut plane, loss = squared colour error to target renders at offset
+    parameters.  Times the forward batch and the adjoint launch (HIP events
+    on the current stream), and the finite-difference gradient the adjoint
+    replaces: central differences need 2 P renders per job (P parameters:
+    c and plane for Julia, n and plane for the Mandelbulb), issued as 2 max(P)
+    batch renders with one parameter of every job offset."""
+    import torch
+
+    import workloads as W
+    from paper_2102_01747_amd.autograd import job_params, job_with_params
+
+    jobs, targets = W.diff_set()
+    frames = frt.render_batch(jobs, dev)
+    tframes = frt.render_batch(targets, dev)
+    torch.cuda.synchronize()
+    gc = [2.0 * (f["colour"] - t["colour"]) for f, t in zip(frames, tframes)]
+    ws_f = frt.alloc_workspace(len(jobs), dev)
+    ws_b = frt.alloc_workspace(len(jobs), dev)
+    grads = None
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        e.synchronize()
+        return s.elapsed_time(e) / reps
+
+    def backward():
+        nonlocal grads
+        grads = frt.render_backward(jobs, frames, gc, None, None, dev, workspace=ws_b, grads=grads)
+
+    t_f = timed(lambda: frt.render_batch(jobs, dev, outs=frames, workspace=ws_f))
+    t_b = timed(backward)
+    slots = [[0, 1, 2, 3, 5, 6, 7, 8] if j["fractal"]["kind"] == "julia" else [4, 5, 6, 7, 8] for j in jobs]
+    n_fd = 2 * max(len(sl) for sl in slots)
+    pert = []
+    for k in range(n_fd):
+        batch = []
+        for j, sl in zip(jobs, slots):
+            row = job_params(j)
+            row[sl[(k // 2) % len(sl)]] += 1e-5 if k % 2 == 0 else -1e-5
+            batch.append(job_with_params(j, row))
+        pert.append(batch)
+    fd_frames = [frt.alloc_frame(j, dev) for j in jobs]
+
+    def fd_all():
+        for batch in pert:
+            frt.render_batch(batch, dev, outs=fd_frames, workspace=ws_f)
+
+    t_fd = timed(fd_all)
+    n = len(jobs)
+    return {"workload": "julia8_mandelbulb8_512x512_cut_plane", "renders": n,
+            "grads_per_s": n / ((t_f + t_b) * 1e-3), "forward_ms": t_f, "backward_ms": t_b,
+            "backward_over_forward": t_b / t_f, "fd_renders_per_gradient": "2 x (8 Julia / 5 Mandelbulb parameters)",
+            "fd_grads_per_s": n / (t_fd * 1e-3), "speedup_vs_fd": (t_fd) / (t_f + t_b),
+            "rel_err_target": 1e-3}
 
 
 def main():
@@ -67,9 +163,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["batch", "single"], default="batch")
-    ap.add_argument("--cpu-stride", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch configuration")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--tune", action="store_true",
+                    help="re-run the autotuner on this workload before timing (default: the recorded tuned.json)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (to scale HBM byte counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -110,11 +208,11 @@ def main():
             for j, f in zip(jobs, frames):
                 frt.render(j, dev, out=f, workspace=ws)
 
-    tuned = None
-    if not args.no_tune:
-        from paper_2102_01747_amd import autotune
+    from paper_2102_01747_amd import autotune
 
-        tuned = autotune.tune(jobs, batch=(args.mode == "batch"), reps=3, passes=2, device=dev)
+    if args.tune:
+        autotune.tune(jobs, batch=(args.mode == "batch"), reps=3, passes=2, device=dev)
+    launch_cfg = dict(zip(autotune.KEYS, frt.autotune_get(autotune.variant_of(jobs))))
 
     # algorithmic work of one step, from the per-pixel counters (untimed)
     cframes = [frt.alloc_frame(j, dev, counters=True) for j in jobs]
@@ -162,7 +260,8 @@ def main():
         try:
             with open(args.traffic) as fh:
                 tr = json.load(fh)
-            if tr.get("workload") == WORKLOAD and tr.get("stage") == dom:
+            if (tr.get("workload") == WORKLOAD and tr.get("stage") == dom and tr.get("launch_config") == launch_cfg
+                    and tr.get("kernel_sources_sha256") == kernel_sources_sha256()):
                 traffic = tr.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
@@ -189,10 +288,12 @@ def main():
                      "stage": dom, "flop_per_launch": stages[dom]["flop"], "launch_ms": stages[dom]["ms"]},
         "stages": stages,
         "whole_path_tflops": float(flops.sum() / (ms_step * 1e-3) / 1e12),
-        "launch_config": tuned["config"] if tuned else "library defaults",
+        "launch_config": launch_cfg,
     }
+    if not args.no_adjoint:
+        rec["adjoint"] = adjoint_leg(frt, dev, max(3, args.steps // 4))
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(jobs, args.cpu_stride)
+        rec["cpu_baseline"] = cpu_baseline(jobs, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
 
 

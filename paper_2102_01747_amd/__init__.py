@@ -100,7 +100,27 @@ def lib():
         L.frt_last_error.argtypes = []
         L.frt_last_error.restype = ctypes.c_char_p
         _lib = L
+        _install_tuned(L)
     return _lib
+
+
+TUNED_PATH = os.path.join(_PKG, "tuned.json")
+
+
+def _install_tuned(L):
+    """Install the launch configurations the autotuner recorded on MI355X
+    (tuned.json, one entry per kernel variant), if present."""
+    if not os.path.exists(TUNED_PATH):
+        return
+    import json
+
+    with open(TUNED_PATH) as fh:
+        data = json.load(fh)
+    for var, c in data.items():
+        st = L.frt_autotune_set(VARIANTS[var], int(c["block"]), int(c["chunk"]), int(c["waves_per_simd"]),
+                                int(c["orbit_lanes"]), int(c["rare_lanes"]))
+        if st != FRT_OK:
+            raise FrtError("tuned.json entry %s rejected: %s" % (var, L.frt_last_error().decode()))
 
 
 def _check(status):

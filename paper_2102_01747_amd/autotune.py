@@ -96,26 +96,48 @@ def tune(jobs, batch=True, reps=5, passes=2, device="cuda", log=None):
     return {"variant": var, "config": cur, "ms": best, "candidates": len(timed)}
 
 
-def load_cache(path, tag):
-    """Install cached settings for `tag` (if the file has them)."""
-    if not os.path.exists(path):
-        return False
-    with open(path) as fh:
-        data = json.load(fh)
-    entry = data.get(tag)
-    if not entry:
-        return False
-    for var, cfg in entry.items():
-        if var in VARIANTS:
-            autotune_set(var, *[cfg[k] for k in KEYS])
-    return True
+TUNED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 
-def save_cache(path, tag, result):
+def save_tuned(result, workload, path=TUNED_PATH):
+    """Record a tune() result as the installed default of its kernel variant
+    (the binding installs tuned.json when it loads the library)."""
     data = {}
     if os.path.exists(path):
         with open(path) as fh:
             data = json.load(fh)
-    data.setdefault(tag, {})[result["variant"]] = result["config"]
+    entry = dict(result["config"])
+    entry["workload"] = workload
+    entry["ms"] = round(float(result["ms"]), 4)
+    data[result["variant"]] = entry
     with open(path, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+
+
+def main():
+    """Tune the launch configuration on one of the reference workloads and
+    record it in tuned.json: python -m paper_2102_01747_amd.autotune WORKLOAD
+    with WORKLOAD one of bulb_views (8 x 1080p Mandelbulb, n = 8),
+    julia_batch (64 uneven Julia renders), diff_set (16 x 512^2, mixed)."""
+    import argparse
+    import sys
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import workloads as W
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("workload", choices=["bulb_views", "julia_batch", "diff_set"])
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--out", default=TUNED_PATH)
+    args = ap.parse_args()
+    jobs = {"bulb_views": W.bulb_views, "julia_batch": W.julia_batch,
+            "diff_set": lambda: W.diff_set()[0]}[args.workload]()
+    res = tune(jobs, batch=True, reps=args.reps, passes=args.passes, log=lambda m: print(m, flush=True))
+    print(json.dumps(res), flush=True)
+    save_tuned(res, args.workload, args.out)
+
+
+if __name__ == "__main__":
+    main()
