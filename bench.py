@@ -28,7 +28,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "primary Mrays/s + % FP32 VALU peak; adjoint grads/s vs FD at rel err 1e-3"
 WORKLOAD = "mandelbulb_n8_1920x1080_8views"
-FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU
+# --workload stress: the 4K power sweep (64 frames, n = 2 + 14 f / 63)
+STRESS = "mandelbulb_sweep_n2_16_3840x2160_64frames"
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk/CU (packed FP32)
+FP32_NONPACKED_PEAK_TFLOPS = 78.6   # the same without packed FP32, which this build does not emit
 
 # Algorithmic FLOP per unit (FMA = 2, add/mul = 1, elementary function = 1):
 #   one orbit body: Julia z^2+c 24; Mandelbulb power map with its derivative 30
@@ -168,6 +171,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--tune", action="store_true",
                     help="re-run the autotuner on this workload before timing (default: the recorded tuned.json)")
+    ap.add_argument("--workload", choices=["bulb_views", "stress"], default="bulb_views",
+                    help="bulb_views: 8 x 1920x1080 Mandelbulb n = 8 (the benchmark); stress: the 4K power sweep")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (to scale HBM byte counters)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -196,7 +201,8 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": n * 4}), flush=True)
         return
 
-    jobs = W.bulb_views()
+    jobs = W.bulb_views() if args.workload == "bulb_views" else W.stress_sweep()
+    wl_name = WORKLOAD if args.workload == "bulb_views" else STRESS
     rays = sum(j["camera"]["width"] * j["camera"]["height"] for j in jobs)
     frames = [frt.alloc_frame(j, dev) for j in jobs]
     ws = frt.alloc_workspace(len(jobs), dev)
@@ -260,12 +266,21 @@ def main():
         try:
             with open(args.traffic) as fh:
                 tr = json.load(fh)
-            if (tr.get("workload") == WORKLOAD and tr.get("stage") == dom and tr.get("launch_config") == launch_cfg
+            if (tr.get("workload") == wl_name and tr.get("stage") == dom and tr.get("launch_config") == launch_cfg
                     and tr.get("kernel_sources_sha256") == kernel_sources_sha256()):
                 traffic = tr.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
 
+    variant = autotune.variant_of(jobs)
+    if args.workload == "bulb_views":
+        config = {"workload": WORKLOAD, "views": len(jobs), "width": 1920, "height": 1080, "power": 8,
+                  "max_iter": 10, "max_steps": 512, "eps_rel": 5e-4, "normals": "central", "shadow": True,
+                  "launch": args.mode, "primary_rays_per_step": rays}
+    else:
+        config = {"workload": STRESS, "frames": len(jobs), "width": 3840, "height": 2160, "power": "2 + 14 f / 63",
+                  "max_iter": 15, "max_steps": 1024, "eps_rel": 2e-4, "normals": "central", "shadow": False,
+                  "plane": "z <= 0.1", "launch": args.mode, "primary_rays_per_step": rays}
     rec = {
         "metric": METRIC,
         "value": rays / (ms_step * 1e-3) / 1e6,
@@ -279,20 +294,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "views": len(jobs), "width": 1920, "height": 1080, "power": 8,
-                   "max_iter": 10, "max_steps": 512, "eps_rel": 5e-4, "normals": "central", "shadow": True,
-                   "launch": args.mode, "primary_rays_per_step": rays},
+        "config": config,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "normal_kernel<bulb8>" if dom == "normals" else "march_kernel<bulb8>",
-                     "stage": dom, "flop_per_launch": stages[dom]["flop"], "launch_ms": stages[dom]["ms"]},
+                     "kernel": ("normal_kernel<%s>" if dom == "normals" else "march_kernel<%s>") % variant,
+                     "stage": dom, "flop_per_launch": stages[dom]["flop"], "launch_ms": stages[dom]["ms"],
+                     "peak_nonpacked_fp32": FP32_NONPACKED_PEAK_TFLOPS,
+                     "frac_of_nonpacked": achieved / FP32_NONPACKED_PEAK_TFLOPS},
         "stages": stages,
         "whole_path_tflops": float(flops.sum() / (ms_step * 1e-3) / 1e12),
         "launch_config": launch_cfg,
     }
-    if not args.no_adjoint:
+    if not args.no_adjoint and args.workload == "bulb_views":
         rec["adjoint"] = adjoint_leg(frt, dev, max(3, args.steps // 4))
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "bulb_views":
         rec["cpu_baseline"] = cpu_baseline(jobs, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
 

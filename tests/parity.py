@@ -83,6 +83,33 @@ def neighbourhood_pixels(pixels, width, height):
     return np.stack(out, 1)
 
 
+def sampled_compare(orc, job, frame, pixels):
+    """Compare a GPU frame (dict of torch tensors or numpy arrays) with the
+    oracle on sampled pixels; the boundary rule uses the oracle's 3x3
+    neighbourhood of every sample."""
+    cam = job["camera"]
+    W_, H = cam["width"], cam["height"]
+    nb = neighbourhood_pixels(pixels, W_, H)
+    o_nb = orc.render(job, pixels=nb.ravel())
+    st_nb = o_nb["status"].reshape(nb.shape)
+    hit_nb, cut_nb = (st_nb & CLS_MASK) >= 2, (st_nb & CLS_MASK) == 3
+    nd = np.any(hit_nb != hit_nb[:, 4:5], 1) | np.any(cut_nb != cut_nb[:, 4:5], 1)
+    o = {k: (v[..., 4::9] if v.ndim == 1 else v[:, 4::9]) for k, v in o_nb.items()}
+    gs = {}
+    for k, v in frame.items():
+        if v is None:
+            continue
+        if hasattr(v, "detach"):
+            import torch
+            idx = torch.as_tensor(pixels, device=v.device)
+            gs[k] = (v[idx] if v.dim() == 1 else v[:, idx]).cpu().numpy()
+        else:
+            gs[k] = v[pixels] if v.ndim == 1 else v[:, pixels]
+    if "counters" in gs:
+        gs["counters"] = gs["counters"].view(np.uint32) if gs["counters"].dtype == np.int32 else gs["counters"]
+    return compare(orc, job, gs, o, nd, pixels=pixels)
+
+
 def normal_ill_conditioned(orc, fr, mc, pts, dirs, eps, seeds=4, tol=2e-4, margin=1e-4):
     """Per point: is the FP64 normal estimate ill-conditioned at float32
     resolution (see the module docstring)?"""

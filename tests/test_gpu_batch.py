@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import workloads as W
-from parity import assert_parity, compare, neighbour_flags, neighbourhood_pixels, to_numpy
+from parity import assert_parity, compare, neighbour_flags, sampled_compare, to_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -58,14 +58,7 @@ def test_batch_parity_against_oracle(frt, orc, batch_jobs):
             st = compare(orc, job, g, o, nd)
         else:
             pix = W.stratified_pixels(W_, H, 8, seed=k)
-            nb = neighbourhood_pixels(pix, W_, H)
-            o_nb = orc.render(job, pixels=nb.ravel())
-            s_nb = o_nb["status"].reshape(nb.shape)
-            hit_nb, cut_nb = (s_nb & 7) >= 2, (s_nb & 7) == 3
-            nd = np.any(hit_nb != hit_nb[:, 4:5], 1) | np.any(cut_nb != cut_nb[:, 4:5], 1)
-            o = {key: (v[..., 4::9] if v.ndim == 1 else v[:, 4::9]) for key, v in o_nb.items()}
-            gs = {key: (v[pix] if v.ndim == 1 else v[:, pix]) for key, v in g.items()}
-            st = compare(orc, job, gs, o, nd, pixels=pix)
+            st = sampled_compare(orc, job, g, pix)
         if st["oracle_hits"] == 0 and st["gpu_hits"] == 0:
             continue
         assert_parity(st)

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import workloads as W
-from parity import assert_parity, compare, neighbour_flags, neighbourhood_pixels, to_numpy
+from parity import assert_parity, compare, neighbour_flags, sampled_compare, to_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -79,15 +79,7 @@ def test_bulb_1080p_views_sampled(frt, orc, view):
     job = W.bulb_views()[view]
     g = _gpu(frt, job)
     pix = W.stratified_pixels(1920, 1080, 16, seed=view)
-    nb = neighbourhood_pixels(pix, 1920, 1080)
-    o_nb = orc.render(job, pixels=nb.ravel())
-    st_nb = o_nb["status"].reshape(nb.shape)
-    hit_nb = (st_nb & 7) >= 2
-    cut_nb = (st_nb & 7) == 3
-    nd = np.any(hit_nb != hit_nb[:, 4:5], 1) | np.any(cut_nb != cut_nb[:, 4:5], 1)
-    o = {k: (v[..., 4::9] if v.ndim == 1 else v[:, 4::9]) for k, v in o_nb.items()}
-    gs = {k: (v[pix] if v.ndim == 1 else v[:, pix]) for k, v in g.items()}
-    st = compare(orc, job, gs, o, nd, pixels=pix)
+    st = sampled_compare(orc, job, g, pix)
     print("view", view, st, flush=True)
     assert_parity(st)
 

@@ -1,0 +1,105 @@
+"""The stress sweep: 64 frames of 3840x2160, frame f with Mandelbulb power
+n = 2 + 14 f / 63 (integer at every 9th frame, real otherwise), cut plane
+z <= 0.1, 15 orbit iterations, 1024 steps, eps = 2e-4 t, central normals.
+
+All 64 frames are rendered in one batched launch (the mixed-kind kernel
+variant: integer and real powers in one index space, 530 M rays) and four
+of them are compared with the FP64 oracle on one pixel per 16x16 cell.  The
+adjoint with respect to n is checked against FP64 central differences on two
+frames at reduced resolution (same cameras), with a seeded N(0, 1) cotangent
+on the colour (L = sum w . colour).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gradcheck import finite_differences
+from parity import adjoint_mask, assert_parity, sampled_compare, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+FRAMES = (0, 20, 45, 63)
+
+
+@pytest.fixture(scope="module")
+def frt():
+    import paper_2102_01747_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def sweep(frt):
+    jobs = W.stress_sweep()
+    frames = frt.render_batch(jobs, "cuda", counters=True)
+    torch.cuda.synchronize()
+    yield jobs, frames
+    del frames
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("f", FRAMES)
+def test_stress_frames_sampled_parity(frt, orc, sweep, f):
+    jobs, frames = sweep
+    pix = W.stratified_pixels(3840, 2160, 16, seed=500 + f)
+    st = sampled_compare(orc, jobs[f], frames[f], pix)
+    print("frame %d (n = %.4f)" % (f, jobs[f]["fractal"]["power"]), st, flush=True)
+    assert st["oracle_hits"] > 1000
+    assert_parity(st)
+
+
+def test_stress_sweep_throughput(frt, sweep):
+    """Times the 64-frame batch (no counters) and checks it renders the same
+    status and depth as the counting launch the parity tests use."""
+    jobs, ref = sweep
+    frames = [frt.alloc_frame(j, "cuda") for j in jobs]
+    ws = frt.alloc_workspace(len(jobs), "cuda")
+    frt.render_batch(jobs, "cuda", outs=frames, workspace=ws)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    reps = 2
+    for _ in range(reps):
+        frt.render_batch(jobs, "cuda", outs=frames, workspace=ws)
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / reps
+    rays = sum(j["camera"]["width"] * j["camera"]["height"] for j in jobs)
+    print("stress sweep: 64 x 3840x2160, %.1f ms per batch, %.0f Mrays/s" % (ms, rays / (ms * 1e-3) / 1e6))
+    for f in FRAMES:
+        assert torch.equal(frames[f]["status"], ref[f]["status"])
+        assert torch.equal(frames[f]["depth"], ref[f]["depth"])
+    del frames
+
+
+@pytest.mark.parametrize("f", (10, 50))
+def test_stress_adjoint_power_vs_fp64_fd(frt, orc, f):
+    job = W.with_size(W.stress_frame(f), 256, 144)
+    fr = frt.render(job, "cuda", counters=True)
+    torch.cuda.synchronize()
+    g = to_numpy(fr)
+    o = orc.render(job)
+    M = adjoint_mask(orc, job, g, o)
+    idx = np.nonzero(M)[0]
+    assert idx.size > 500, idx.size
+    J, taps = orc.pixel_jacobian(job, idx)
+    scale = 1.0 + np.abs(J.transpose(1, 0, 2))
+    fd, stable = finite_differences(orc, job, idx, [4], o["status"][idx], taps, scale)
+    keep = stable[4]
+    assert keep.mean() > 0.95, keep.mean()
+    P = job["camera"]["width"] * job["camera"]["height"]
+    w = np.random.default_rng(5).normal(size=(3, P)).astype(np.float32)
+    M2 = np.zeros(P, bool)
+    M2[idx[keep]] = True
+    w[:, ~M2] = 0.0
+    gc = torch.from_numpy(w).cuda()
+    grads = frt.render_backward([job], [fr], [gc], None, None, "cuda")
+    torch.cuda.synchronize()
+    gpu = float(grads[1].cpu()[0])
+    ref = float(np.sum(w[:, idx] * fd[4][4:7]))
+    scale_sum = float(np.sum(np.abs(w[:, idx] * fd[4][4:7])))
+    rel = abs(gpu - ref) / abs(ref)
+    print("frame %d (n = %.4f): dL/dn GPU %.8e FD %.8e rel %.2e (sum |terms| %.3e)"
+          % (f, job["fractal"]["power"], gpu, ref, rel, scale_sum))
+    assert rel < 1e-3
