@@ -218,7 +218,8 @@ def main():
 
     if args.tune:
         autotune.tune(jobs, batch=(args.mode == "batch"), reps=3, passes=2, device=dev)
-    launch_cfg = dict(zip(autotune.KEYS, frt.autotune_get(autotune.variant_of(jobs))))
+    variants = autotune.variants_of(jobs)
+    launch_cfg = {v: dict(zip(autotune.KEYS, frt.autotune_get(v))) for v in variants}
 
     # algorithmic work of one step, from the per-pixel counters (untimed)
     cframes = [frt.alloc_frame(j, dev, counters=True) for j in jobs]
@@ -266,13 +267,14 @@ def main():
         try:
             with open(args.traffic) as fh:
                 tr = json.load(fh)
-            if (tr.get("workload") == wl_name and tr.get("stage") == dom and tr.get("launch_config") == launch_cfg
+            if (tr.get("workload") == wl_name and tr.get("stage") == dom and len(variants) == 1
+                    and tr.get("launch_config") == launch_cfg[variants[0]]
                     and tr.get("kernel_sources_sha256") == kernel_sources_sha256()):
                 traffic = tr.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
 
-    variant = autotune.variant_of(jobs)
+    variant = "+".join(variants)
     if args.workload == "bulb_views":
         config = {"workload": WORKLOAD, "views": len(jobs), "width": 1920, "height": 1080, "power": 8,
                   "max_iter": 10, "max_steps": 512, "eps_rel": 5e-4, "normals": "central", "shadow": True,

@@ -161,12 +161,15 @@ frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_
                       int32_t n_planes, const frt_march* march, frt_frame out,
                       void* workspace, size_t ws_bytes, void* stream);
 
-/* Render n_jobs independent views in one persistent launch: the rays of all
- * jobs form one index space that waves drain through a shared queue.
+/* Render n_jobs independent views in one persistent launch per kernel
+ * variant present (Julia, Mandelbulb with real, integer or n = 8 power): the
+ * rays of a variant's jobs form one index space that its waves drain through
+ * a shared queue.
  * jobs: host array of n_jobs (>= 1) entries; workspace: device memory of
  * frt_workspace_bytes(n_jobs) bytes.  use_graph = 1 replays a HIP graph of
- * the launch captured on the first call with the same (workspace, stream,
- * job kinds); the job table is re-uploaded before every replay, so
+ * the launches captured on the first call with the same (workspace,
+ * variants present, launch settings); the job table is re-uploaded before
+ * every replay, so
  * parameters and output pointers may change between calls.
  * Errors as frt_render; a job's index appears in frt_last_error().         */
 frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace, size_t ws_bytes,
@@ -221,7 +224,8 @@ frt_status frt_math_eval(int32_t func, const float* x, const float* y, float* ou
 
 /* Launch configuration of the persistent kernels, chosen by the autotuner.
  * kernel_variant: 0 Julia, 1 Mandelbulb (real n), 2 Mandelbulb (integer n),
- * 3 mixed kinds, 4 Mandelbulb with n = 8 (the power the paper renders).
+ * 3 Mandelbulb with n = 8 (the power the paper renders).  A batch is traced
+ * as one group of rays per variant present, each with its own setting.
  * block: 64, 128, 256 or 512 threads; chunk: rays taken from the queue per
  * refill, a multiple of 64 in [64, 4096]; waves_per_simd: resident waves per
  * SIMD the grid is sized for, [1, 8] (0 = occupancy limit);

@@ -28,17 +28,27 @@ SPACE = {
 KEYS = ["block", "chunk", "waves_per_simd", "orbit_lanes", "rare_lanes"]
 
 
-def variant_of(jobs):
-    """Kernel variant the library picks for these jobs."""
-    kinds = set()
+def variants_of(jobs):
+    """Kernel variants the library traces these jobs with (one group each)."""
+    out = []
     for j in jobs:
         fr = j["fractal"]
         if fr["kind"] == "julia":
-            kinds.add("julia")
+            v = "julia"
         else:
             n = float(fr["power"])
-            kinds.add("bulb8" if n == 8.0 else ("bulb_int" if n.is_integer() and 2 <= n <= 64 else "bulb_real"))
-    return kinds.pop() if len(kinds) == 1 else "mixed"
+            v = "bulb8" if n == 8.0 else ("bulb_int" if n.is_integer() and 2 <= n <= 64 else "bulb_real")
+        if v not in out:
+            out.append(v)
+    return out
+
+
+def variant_of(jobs):
+    """The single variant of a one-variant job list."""
+    vs = variants_of(jobs)
+    if len(vs) != 1:
+        raise ValueError("jobs use several kernel variants: %s" % vs)
+    return vs[0]
 
 
 def time_config(jobs, frames, ws, batch, reps=5, device="cuda"):
@@ -64,36 +74,39 @@ def time_config(jobs, frames, ws, batch, reps=5, device="cuda"):
 
 
 def tune(jobs, batch=True, reps=5, passes=2, device="cuda", log=None):
-    """Coordinate descent over SPACE; installs and returns the best config
-    as a dict together with its time in ms."""
-    var = variant_of(jobs)
+    """Coordinate descent over SPACE for every variant the jobs use (each
+    timed on the whole batch, the others held at their current setting);
+    installs the best settings and returns them per variant with the time."""
     frames = [alloc_frame(j, device) for j in jobs]
     ws = alloc_workspace(len(jobs), device)
-    cur = dict(zip(KEYS, autotune_get(var)))
-    timed = {}
+    results = []
+    for var in variants_of(jobs):
+        cur = dict(zip(KEYS, autotune_get(var)))
+        timed = {}
 
-    def measure(cfg):
-        key = tuple(cfg[k] for k in KEYS)
-        if key not in timed:
-            autotune_set(var, *key)
-            timed[key] = time_config(jobs, frames, ws, batch, reps, device)
-            if log:
-                log("  %s %.3f ms" % (dict(zip(KEYS, key)), timed[key]))
-        return timed[key]
+        def measure(cfg):
+            key = tuple(cfg[k] for k in KEYS)
+            if key not in timed:
+                autotune_set(var, *key)
+                timed[key] = time_config(jobs, frames, ws, batch, reps, device)
+                if log:
+                    log("  %s %s %.3f ms" % (var, dict(zip(KEYS, key)), timed[key]))
+            return timed[key]
 
-    best = measure(cur)
-    for _ in range(passes):
-        improved = False
-        for k in KEYS:
-            for v in SPACE[k]:
-                cand = dict(cur, **{k: v})
-                t = measure(cand)
-                if t < best * 0.995:
-                    best, cur, improved = t, cand, True
-        if not improved:
-            break
-    autotune_set(var, *[cur[k] for k in KEYS])
-    return {"variant": var, "config": cur, "ms": best, "candidates": len(timed)}
+        best = measure(cur)
+        for _ in range(passes):
+            improved = False
+            for k in KEYS:
+                for v in SPACE[k]:
+                    cand = dict(cur, **{k: v})
+                    t = measure(cand)
+                    if t < best * 0.995:
+                        best, cur, improved = t, cand, True
+            if not improved:
+                break
+        autotune_set(var, *[cur[k] for k in KEYS])
+        results.append({"variant": var, "config": cur, "ms": best, "candidates": len(timed)})
+    return results
 
 
 TUNED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
@@ -119,7 +132,8 @@ def main():
     """Tune the launch configuration on one of the reference workloads and
     record it in tuned.json: python -m paper_2102_01747_amd.autotune WORKLOAD
     with WORKLOAD one of bulb_views (8 x 1080p Mandelbulb, n = 8),
-    julia_batch (64 uneven Julia renders), diff_set (16 x 512^2, mixed)."""
+    julia_batch (64 uneven Julia renders), diff_set (16 x 512^2, Julia and
+    Mandelbulb), stress (the 4K power sweep: real and integer powers)."""
     import argparse
     import sys
 
@@ -127,16 +141,16 @@ def main():
     import workloads as W
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("workload", choices=["bulb_views", "julia_batch", "diff_set"])
+    ap.add_argument("workload", choices=["bulb_views", "julia_batch", "diff_set", "stress"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--out", default=TUNED_PATH)
     args = ap.parse_args()
     jobs = {"bulb_views": W.bulb_views, "julia_batch": W.julia_batch,
-            "diff_set": lambda: W.diff_set()[0]}[args.workload]()
-    res = tune(jobs, batch=True, reps=args.reps, passes=args.passes, log=lambda m: print(m, flush=True))
-    print(json.dumps(res), flush=True)
-    save_tuned(res, args.workload, args.out)
+            "diff_set": lambda: W.diff_set()[0], "stress": W.stress_sweep}[args.workload]()
+    for res in tune(jobs, batch=True, reps=args.reps, passes=args.passes, log=lambda m: print(m, flush=True)):
+        print(json.dumps(res), flush=True)
+        save_tuned(res, args.workload, args.out)
 
 
 if __name__ == "__main__":

@@ -64,7 +64,6 @@ Tune g_tune[frt::kNumVariants] = {
     {64, 256, 0, 8, 16},   // Julia
     {64, 256, 0, 8, 16},   // Mandelbulb, real power
     {64, 256, 0, 8, 16},   // Mandelbulb, integer power
-    {64, 256, 0, 8, 16},   // mixed
     {64, 256, 0, 8, 16},   // Mandelbulb, n = 8
 };
 
@@ -311,12 +310,22 @@ Staging g_stage;
 
 struct GraphEntry {
     void* workspace;
-    int variant;
-    LaunchCfg cfg;
+    std::vector<frt::TraceGroup> groups;
     int device;
-    bool any_shadow;
     hipGraphExec_t exec;
 };
+
+bool same_groups(const std::vector<frt::TraceGroup>& a, const std::vector<frt::TraceGroup>& b) {
+    if (a.size() != b.size()) return false;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const LaunchCfg &x = a[i].cfg, &y = b[i].cfg;
+        if (a[i].variant != b[i].variant || a[i].any_shadow != b[i].any_shadow || x.grid != y.grid ||
+            x.normal_grid != y.normal_grid || x.block != y.block || x.chunk != y.chunk ||
+            x.orbit_lanes != y.orbit_lanes || x.rare_lanes != y.rare_lanes)
+            return false;
+    }
+    return true;
+}
 std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;
 hipStream_t g_capture_stream = nullptr;
@@ -384,11 +393,13 @@ frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_
     if (s != FRT_OK) return s;
     JobDev J;
     pack(cam, frac, planes, n_planes, march, out, 0, J);
-    const int var = variant_of(J);
-    LaunchCfg cfg;
-    if (!make_cfg(frt::trace_kernel_symbol(var, false), var, J.ray_count, cfg, why)) return fail(FRT_EHIP, why);
-    hipError_t e = frt::launch_trace(var, false, cfg, nullptr, J, static_cast<WorkspaceHeader*>(workspace),
-                                     J.shadow != 0, static_cast<hipStream_t>(stream), timing_marks());
+    frt::TraceGroup g;
+    g.variant = variant_of(J);
+    g.any_shadow = J.shadow != 0;
+    if (!make_cfg(frt::trace_kernel_symbol(g.variant, false), g.variant, J.ray_count, g.cfg, why))
+        return fail(FRT_EHIP, why);
+    hipError_t e = frt::launch_trace(&g, 1, false, nullptr, J, static_cast<WorkspaceHeader*>(workspace),
+                                     static_cast<hipStream_t>(stream), timing_marks());
     if (e != hipSuccess) return hip_fail(e, "trace launch");
     return FRT_OK;
 }
@@ -400,35 +411,56 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
     if (use_graph != 0 && use_graph != 1) return fail(FRT_EINVAL, "use_graph must be 0 or 1");
     frt_status s = check_workspace(workspace, ws_bytes, n_jobs);
     if (s != FRT_OK) return s;
-    std::vector<JobDev> table(static_cast<size_t>(n_jobs));
-    int64_t begin = 0;
-    int var = -1;
-    bool any_shadow = false;
+    // pack every job, then lay the rays out variant by variant: group v is
+    // one contiguous range of the ray index space traced by its own kernels
+    // (the table order is internal; outputs travel with each job)
+    std::vector<JobDev> packed(static_cast<size_t>(n_jobs));
+    std::vector<int> var_of(static_cast<size_t>(n_jobs));
     for (int i = 0; i < n_jobs; ++i) {
         std::string why;
         const frt_job& jb = jobs[i];
         if (!validate(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, &jb.out, true, why))
             return fail(FRT_EINVAL, "job " + std::to_string(i) + ": " + why);
-        pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, begin, table[size_t(i)]);
-        begin += table[size_t(i)].ray_count;
-        any_shadow = any_shadow || table[size_t(i)].shadow != 0;
-        const int v = variant_of(table[size_t(i)]);
-        var = (var < 0 || var == v) ? v : frt::kVarMixed;
+        pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, 0, packed[size_t(i)]);
+        var_of[size_t(i)] = variant_of(packed[size_t(i)]);
     }
     WorkspaceHeader hdr;
     std::memset(&hdr, 0, sizeof(hdr));
+    std::vector<JobDev> table;
+    table.reserve(size_t(n_jobs));
+    std::vector<frt::TraceGroup> groups;
+    int64_t begin = 0;
+    for (int v = 0; v < frt::kNumVariants; ++v) {
+        const int64_t g0 = begin;
+        bool shadow = false;
+        for (int i = 0; i < n_jobs; ++i) {
+            if (var_of[size_t(i)] != v) continue;
+            JobDev J = packed[size_t(i)];
+            J.ray_begin = begin;
+            begin += J.ray_count;
+            shadow = shadow || J.shadow != 0;
+            table.push_back(J);
+        }
+        hdr.range[v][0] = static_cast<unsigned long long>(g0);
+        hdr.range[v][1] = static_cast<unsigned long long>(begin);
+        if (begin == g0) continue;
+        frt::TraceGroup g;
+        g.variant = v;
+        g.any_shadow = shadow;
+        std::string why;
+        if (!make_cfg(frt::trace_kernel_symbol(v, true), v, begin - g0, g.cfg, why)) return fail(FRT_EHIP, why);
+        groups.push_back(g);
+    }
     hdr.total_rays = static_cast<unsigned long long>(begin);
     hdr.n_jobs = n_jobs;
     hipStream_t st = static_cast<hipStream_t>(stream);
     s = upload_table(table, hdr, workspace, st);
     if (s != FRT_OK) return s;
     const JobDev* dev_jobs = reinterpret_cast<const JobDev*>(static_cast<char*>(workspace) + sizeof(WorkspaceHeader));
-    std::string why;
-    LaunchCfg cfg;
-    if (!make_cfg(frt::trace_kernel_symbol(var, true), var, begin, cfg, why)) return fail(FRT_EHIP, why);
     WorkspaceHeader* dhdr = static_cast<WorkspaceHeader*>(workspace);
+    const int ng = static_cast<int>(groups.size());
     if (!use_graph) {
-        hipError_t e = frt::launch_trace(var, true, cfg, dev_jobs, table[0], dhdr, any_shadow, st, timing_marks());
+        hipError_t e = frt::launch_trace(groups.data(), ng, true, dev_jobs, table[0], dhdr, st, timing_marks());
         if (e != hipSuccess) return hip_fail(e, "trace launch");
         return FRT_OK;
     }
@@ -437,9 +469,7 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
     std::lock_guard<std::mutex> lk(g_graph_mu);
     hipGraphExec_t exec = nullptr;
     for (const GraphEntry& g : g_graphs) {
-        if (g.workspace == workspace && g.variant == var && g.device == dev && g.any_shadow == any_shadow &&
-            g.cfg.grid == cfg.grid && g.cfg.block == cfg.block && g.cfg.chunk == cfg.chunk &&
-            g.cfg.orbit_lanes == cfg.orbit_lanes && g.cfg.rare_lanes == cfg.rare_lanes) {
+        if (g.workspace == workspace && g.device == dev && same_groups(g.groups, groups)) {
             exec = g.exec;
             break;
         }
@@ -452,7 +482,7 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
         }
         e = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        hipError_t le = frt::launch_trace(var, true, cfg, dev_jobs, table[0], dhdr, any_shadow, g_capture_stream);
+        hipError_t le = frt::launch_trace(groups.data(), ng, true, dev_jobs, table[0], dhdr, g_capture_stream);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(g_capture_stream, &graph);
         if (le != hipSuccess) {
@@ -463,7 +493,7 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-        g_graphs.push_back(GraphEntry{workspace, var, cfg, dev, any_shadow, exec});
+        g_graphs.push_back(GraphEntry{workspace, groups, dev, exec});
     }
     e = hipGraphLaunch(exec, st);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");

@@ -6,10 +6,13 @@
 // max_iter bodies or when |z|^2 exceeds bailout2; `it` counts the bodies whose
 // result stayed within the bailout (it == max_iter: no escape).
 //
-// The estimators are written as resumable orbit states (init / step / result)
-// so that the persistent kernel can advance every lane by a few bodies per
-// trip and let lanes whose orbit has ended move on to their next sample
-// without waiting for the slowest lane of the wave.
+// The estimators are written as resumable orbit states (init / body /
+// result) so that the persistent kernel can advance every lane by a few
+// bodies per trip and let lanes whose orbit has ended move on to their next
+// sample without waiting for the slowest lane of the wave.  body() returns
+// whether the orbit is still within the bailout; the caller stops a lane when
+// it returns false or after max_iter bodies (k counts the bodies run), so the
+// hot loop carries no per-lane escape flag.
 #pragma once
 
 #include "frt_math.hpp"
@@ -24,6 +27,8 @@ struct DEResult {
 
 // 0.25 ln(m) folded into the log2 hardware op
 constexpr float kQuarterLn2 = 0.25f * kLn2;
+// floor under |w|^2 and rho^2 before a reciprocal square root (keeps rsq finite)
+constexpr float kTinyFloor = 1e-30f;
 
 // Parameters the orbit bodies read.
 struct OrbitParams {
@@ -46,17 +51,14 @@ struct OrbitParams {
 struct JuliaOrbit {
     float a, b, e, w, m2, prod;
     int k;
-    bool esc;
 
     __device__ __forceinline__ void init(float x, float y, float z) {
         a = x; b = y; e = z; w = 0.0f;
         m2 = fmaf(a, a, fmaf(b, b, e * e));
         prod = 1.0f;
         k = 0;
-        esc = false;
     }
-    __device__ __forceinline__ bool done(const OrbitParams& P) const { return esc || k >= P.max_iter; }
-    __device__ __forceinline__ void body(const OrbitParams& P) {
+    __device__ __forceinline__ bool body(const OrbitParams& P) {
         prod *= m2;
         const float vv = fmaf(b, b, fmaf(e, e, w * w));
         const float a2 = a + a;
@@ -66,13 +68,15 @@ struct JuliaOrbit {
         w = fmaf(a2, w, P.c3);
         a = na;
         m2 = fmaf(a, a, fmaf(b, b, fmaf(e, e, w * w)));
-        if (m2 > P.bail2) esc = true; else ++k;
+        ++k;
+        return !(m2 > P.bail2);
     }
-    __device__ __forceinline__ DEResult result() const {
+    __device__ __forceinline__ DEResult result(const OrbitParams& P) const {
         DEResult r;
-        r.bodies = esc ? k + 1 : k;
-        r.it = k;
-        const float dz2 = ldexpf(prod, 2 * r.bodies);
+        const bool esc = m2 > P.bail2;
+        r.bodies = k;
+        r.it = esc ? k - 1 : k;
+        const float dz2 = ldexpf(prod, 2 * k);
         r.d = m2 > 0.0f ? kQuarterLn2 * hw_log2(m2) * (m2 * hw_rsq(m2)) * hw_rsq(dz2) : 0.0f;
         return r;
     }
@@ -96,7 +100,6 @@ template <int MODE>
 struct BulbOrbit {
     float wx, wy, wz, m, dr, px, py, pz;
     int k;
-    bool esc;
 
     __device__ __forceinline__ void init(float x, float y, float z) {
         wx = x; wy = y; wz = z;
@@ -104,10 +107,8 @@ struct BulbOrbit {
         m = fmaf(x, x, fmaf(y, y, z * z));
         dr = 1.0f;
         k = 0;
-        esc = false;
     }
-    __device__ __forceinline__ bool done(const OrbitParams& P) const { return esc || k >= P.max_iter; }
-    __device__ __forceinline__ void body(const OrbitParams& P) {
+    __device__ __forceinline__ bool body(const OrbitParams& P) {
         if constexpr (MODE == 0) {
             const float rn1 = hw_exp2(P.nm1_half * hw_log2(m));
             dr = fmaf(P.n * rn1, dr, 1.0f);
@@ -123,17 +124,26 @@ struct BulbOrbit {
             const float nz = fmaf(rsb, hw_cos_rev(at), pz);
             wx = nx; wy = ny; wz = nz;
         } else {
-            const float rinv = m > 0.0f ? hw_rsq(m) : 0.0f;
-            const float r = m * rinv;
-            const float rho2 = fmaf(wx, wx, wz * wz);
-            const float irho = rho2 > 0.0f ? hw_rsq(rho2) : 0.0f;
+            // tiny floors instead of branches: at r = 0 or rho = 0 the
+            // factors they scale are zero (r^(n-1) dr, and Im Y = 0 on the
+            // polar axis), so the floor changes no result
+            const float rho2 = fmaxf(fmaf(wx, wx, wz * wz), kTinyFloor);
+            const float irho = hw_rsq(rho2);
             float yr = wy, yi = rho2 * irho;
-            float zr = rho2 > 0.0f ? wz * irho : 1.0f, zi = wx * irho;
+            float zr = wz * irho, zi = wx * irho;
             if constexpr (MODE > 0) {
-                dr = fmaf(static_cast<float>(MODE) * ipow_c<MODE - 1>(r), dr, 1.0f);
+                // r^(n-1) = m^(n/2) / r for even n, m^((n-1)/2) for odd n
+                if constexpr ((MODE & 1) == 0) {
+                    const float rinv = hw_rsq(fmaxf(m, kTinyFloor));
+                    dr = fmaf(static_cast<float>(MODE) * (ipow_c<MODE / 2>(m) * rinv), dr, 1.0f);
+                } else {
+                    dr = fmaf(static_cast<float>(MODE) * ipow_c<(MODE - 1) / 2>(m), dr, 1.0f);
+                }
                 cpow_c<MODE>(yr, yi);
                 cpow_c<MODE>(zr, zi);
             } else {
+                const float rinv = hw_rsq(fmaxf(m, kTinyFloor));
+                const float r = m * rinv;
                 dr = fmaf(P.n * ipow(r, P.ipow - 1), dr, 1.0f);
                 cpow_int(yr, yi, P.ipow);
                 cpow_int(zr, zi, P.ipow);
@@ -143,47 +153,26 @@ struct BulbOrbit {
             wz = fmaf(yi, zr, pz);
         }
         m = fmaf(wx, wx, fmaf(wy, wy, wz * wz));
-        if (m > P.bail2) esc = true; else ++k;
+        ++k;
+        return !(m > P.bail2);
     }
-    __device__ __forceinline__ DEResult result() const {
+    __device__ __forceinline__ DEResult result(const OrbitParams& P) const {
         DEResult r;
-        r.bodies = esc ? k + 1 : k;
-        r.it = k;
+        const bool esc = m > P.bail2;
+        r.bodies = k;
+        r.it = esc ? k - 1 : k;
         r.d = m > 0.0f ? kQuarterLn2 * hw_log2(m) * (m * hw_rsq(m)) * hw_rcp(dr) : 0.0f;
         return r;
     }
 };
 
-// Julia or any Mandelbulb mode chosen per lane (batches that mix kinds).
-struct MixedOrbit {
-    JuliaOrbit j;
-    BulbOrbit<0> br;
-    BulbOrbit<-1> bi;
-    int sel;   // 0 Julia, 1 real power, 2 integer power
-
-    __device__ __forceinline__ void set_kind(const OrbitParams& P) {
-        sel = P.kind == 0 ? 0 : (P.ipow > 0 ? 2 : 1);
-    }
-    __device__ __forceinline__ void init(float x, float y, float z) {
-        if (sel == 0) j.init(x, y, z); else if (sel == 1) br.init(x, y, z); else bi.init(x, y, z);
-    }
-    __device__ __forceinline__ bool done(const OrbitParams& P) const {
-        return sel == 0 ? j.done(P) : (sel == 1 ? br.done(P) : bi.done(P));
-    }
-    __device__ __forceinline__ void body(const OrbitParams& P) {
-        if (sel == 0) j.body(P); else if (sel == 1) br.body(P); else bi.body(P);
-    }
-    __device__ __forceinline__ DEResult result() const {
-        return sel == 0 ? j.result() : (sel == 1 ? br.result() : bi.result());
-    }
-};
-
-// One-shot estimate (all bodies at once) with any orbit type.
+// One-shot estimate (all bodies at once) with any orbit type; max_iter >= 1.
 template <class O>
 __device__ __forceinline__ DEResult de_once(O& o, const OrbitParams& P, float x, float y, float z) {
     o.init(x, y, z);
-    while (!o.done(P)) o.body(P);
-    return o.result();
+    while (o.body(P) && o.k < P.max_iter) {
+    }
+    return o.result(P);
 }
 
 }  // namespace frt

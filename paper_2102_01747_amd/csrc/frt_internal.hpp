@@ -16,15 +16,23 @@ struct LaunchCfg {
     int rare_lanes;       // waiting lanes that trigger shading / refill
 };
 
+// One group of a forward launch: the rays of one kernel variant.
+struct TraceGroup {
+    int variant;
+    LaunchCfg cfg;
+    bool any_shadow;   // some job of the group casts shadow rays
+};
+
 // Forward pass: resets the ray queues in the workspace header, then launches
-// the primary march, the normal kernel and (if any_shadow) the shadow march.
-// batch = false reads the job from `job1` (kernel argument); batch = true
-// reads `jobs` (device table) and the ray count from `hdr`.
+// the primary march of every group, the normal kernel of every group and the
+// shadow march of every group that has shadow rays.  batch = false reads the
+// job from `job1` (kernel argument, one group); batch = true reads `jobs`
+// (device table) and each group's ray range from `hdr`.
 // marks[0..3] (optional, may be null): events recorded on `stream` before the
-// primary march, before the normal kernel, before the shadow march and after
-// the last kernel.
-hipError_t launch_trace(int variant, bool batch, const LaunchCfg& cfg, const JobDev* jobs, const JobDev& job1,
-                        WorkspaceHeader* hdr, bool any_shadow, hipStream_t stream, hipEvent_t* marks = nullptr);
+// primary marches, before the normal kernels, before the shadow marches and
+// after the last kernel.
+hipError_t launch_trace(const TraceGroup* groups, int n_groups, bool batch, const JobDev* jobs, const JobDev& job1,
+                        WorkspaceHeader* hdr, hipStream_t stream, hipEvent_t* marks = nullptr);
 const void* trace_kernel_symbol(int variant, bool batch);
 
 // Point queries (frt_query.hip).

@@ -9,14 +9,14 @@ namespace frt {
 
 enum Kind : int32_t { kJulia = 0, kBulb = 1 };
 
-// kernel variants (template argument and autotuner key)
+// kernel variants (template argument and autotuner key); a batch is split
+// into one group of rays per variant present, each traced by its own kernels
 enum Variant : int32_t {
     kVarJulia = 0,      // quaternion Julia
     kVarBulbReal = 1,   // Mandelbulb, real power (trigonometric map)
     kVarBulbInt = 2,    // Mandelbulb, integer power read at run time
-    kVarMixed = 3,      // several kinds in one batch
-    kVarBulb8 = 4,      // Mandelbulb, power 8 fixed at compile time
-    kNumVariants = 5
+    kVarBulb8 = 3,      // Mandelbulb, power 8 fixed at compile time
+    kNumVariants = 4
 };
 
 // status byte
@@ -86,21 +86,18 @@ struct AdjointJob {
     float raw_n[2][3];       // raw plane normals (the job holds unit ones)
 };
 
-// The ray index space of a launch can be split into kQueues contiguous
-// segments, each drained through its own counter (waves start on their
-// workgroup's segment and move on when it is drained).  Measured on the
-// 1080p Mandelbulb batch, one queue with 256-ray claims was fastest (32
-// segments: 5.7 ms vs 4.7 ms per step), so one segment is used.
-constexpr int kQueues = 1;
-
 // Workspace layout: a 1 KiB header, the job table, then the table of
-// upstream-gradient pointers (AdjointJob, read by the adjoint only).
+// upstream-gradient pointers (AdjointJob, read by the adjoint only).  The jobs
+// of a batch are laid out in the ray index space variant by variant; group v
+// holds the rays [range[v][0], range[v][1]) and drains them through its own
+// counters (one for the primary march, one for the shadow march).
 struct alignas(256) WorkspaceHeader {
-    unsigned long long queue[2][kQueues];   // claimed rays per segment: primary march, shadow march
-    unsigned long long adj_queue[2];        // 64-ray tiles claimed by the adjoint kernels (per kind)
+    unsigned long long queue[kNumVariants][2];   // rays claimed: primary march, shadow march
+    unsigned long long range[kNumVariants][2];   // each group's [begin, end) in the ray index space
+    unsigned long long adj_queue[2];             // 64-ray tiles claimed by the adjoint kernels (per kind)
     unsigned long long total_rays;
     int32_t n_jobs;
-    int32_t pad[(1024 - 16 * kQueues - 28) / 4];
+    int32_t pad[(1024 - 32 * kNumVariants - 28) / 4];
 };
 static_assert(sizeof(WorkspaceHeader) == 1024, "workspace header must be 1 KiB");
 

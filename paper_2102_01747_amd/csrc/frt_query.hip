@@ -3,8 +3,6 @@
 // library's fast float32 transcendentals, for accuracy checks.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "frt_fractal.hpp"
 #include "frt_internal.hpp"
 #include "frt_job.hpp"
@@ -17,7 +15,6 @@ __global__ void __launch_bounds__(256) distance_kernel(OrbitParams P, const floa
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     O o;
-    if constexpr (std::is_same_v<O, MixedOrbit>) o.set_kind(P);
     const DEResult r = de_once(o, P, pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]);
     d[i] = r.d;
     if (it) it[i] = r.it;
@@ -37,11 +34,8 @@ hipError_t launch_distance(int variant, const OrbitParams& P, const float* pts, 
         case kVarBulbInt:
             hipLaunchKernelGGL(distance_kernel<BulbOrbit<-1>>, dim3(grid), dim3(block), 0, stream, P, pts, n, d, it);
             break;
-        case kVarBulb8:
-            hipLaunchKernelGGL(distance_kernel<BulbOrbit<8>>, dim3(grid), dim3(block), 0, stream, P, pts, n, d, it);
-            break;
         default:
-            hipLaunchKernelGGL(distance_kernel<MixedOrbit>, dim3(grid), dim3(block), 0, stream, P, pts, n, d, it);
+            hipLaunchKernelGGL(distance_kernel<BulbOrbit<8>>, dim3(grid), dim3(block), 0, stream, P, pts, n, d, it);
             break;
     }
     return hipGetLastError();

@@ -31,7 +31,10 @@
 
 namespace frt {
 
-// Refinement stops once the root bracket is narrower than eps(t) / 32.
+// Bisection stops once the root bracket is narrower than eps(t) / 32 (then one
+// secant step on the final bracket).  A coarser bracket keeps the depth within
+// tolerance but moves the normal taps with it; the bisection also picks the
+// same root as the oracle's when a step holds several crossings.
 constexpr float kRefineTol = 1.0f / 32.0f;
 // Upper bound on orbit bodies per loop trip (keeps finished rays flowing).
 constexpr int kMaxBodiesPerTrip = 64;
@@ -41,7 +44,6 @@ template <> struct OrbitOf<kVarJulia> { using T = JuliaOrbit; };
 template <> struct OrbitOf<kVarBulbReal> { using T = BulbOrbit<0>; };
 template <> struct OrbitOf<kVarBulbInt> { using T = BulbOrbit<-1>; };
 template <> struct OrbitOf<kVarBulb8> { using T = BulbOrbit<8>; };
-template <> struct OrbitOf<kVarMixed> { using T = MixedOrbit; };
 
 enum MarchPhase : int { kIdle = 0, kCut = 1, kMarch = 2, kRefine = 3, kDone = 4 };
 
@@ -56,18 +58,16 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                                                     WorkspaceHeader* __restrict__ hdr, int chunk,
                                                     int orbit_lanes, int rare_lanes) {
     using Orbit = typename OrbitOf<VAR>::T;
-    unsigned long long* queues = hdr->queue[SHADOW ? 1 : 0];
+    // this variant's group of rays and its counter
+    unsigned long long* queue = &hdr->queue[VAR][SHADOW ? 1 : 0];
     int n_jobs = 1;
-    unsigned long long total_rays = static_cast<unsigned long long>(job1.ray_count);
+    unsigned long long r_begin = 0, r_end = static_cast<unsigned long long>(job1.ray_count);
     if constexpr (BATCH) {
         n_jobs = hdr->n_jobs;
-        total_rays = hdr->total_rays;
+        r_begin = hdr->range[VAR][0];
+        r_end = hdr->range[VAR][1];
     }
-    // segments of the ray index space (multiples of 64 rays); a wave starts on
-    // the segment of its workgroup and moves on when that one is drained
-    const unsigned long long seg = ((total_rays + kQueues * 64ull - 1) / (kQueues * 64ull)) * 64ull;
-    int qi = static_cast<int>(blockIdx.x % kQueues), q_tries = 0;
-    unsigned long long q_next = 0, q_end = 0;   // wave-uniform queue window
+    unsigned long long q_next = 0, q_end = 0;   // wave-uniform window of claimed rays
     bool drained = false;
 
     int phase = kIdle;
@@ -75,9 +75,12 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
     unsigned evals = 0, bodies = 0;
     float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 1.f;
     float t = 0.f, t1 = 0.f, lt = 0.f, lh = 0.f, gb = 0.f, ea = 0.f, er = 0.f;
+    // march settings of the lane's job, copied when the ray is claimed
+    float clamp = 0.2f;
+    int max_steps = 1, refine_iters = 0;
+    bool live = false;   // the lane's orbit is still iterating
     OrbitParams P = orbit_params(job1);
     Orbit orb;
-    if constexpr (VAR == kVarMixed) orb.set_kind(P);
 
     for (;;) {
         // ------------------------------------------ finished rays + refill
@@ -133,18 +136,15 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
             unsigned long long idle = __ballot(phase == kIdle);
             while (idle != 0ull && !drained) {
                 if (q_next >= q_end) {
-                    const unsigned long long s0 = static_cast<unsigned long long>(qi) * seg;
-                    const unsigned long long s1 = min(s0 + seg, total_rays);
                     unsigned long long base = 0;
-                    if (__lane_id() == 0) base = atomicAdd(&queues[qi], static_cast<unsigned long long>(chunk));
-                    base = s0 + bcast_first(base);
-                    if (base >= s1) {   // segment drained: try the next one
-                        qi = (qi + 1) % kQueues;
-                        if (++q_tries == kQueues) drained = true;
+                    if (__lane_id() == 0) base = atomicAdd(queue, static_cast<unsigned long long>(chunk));
+                    base = r_begin + bcast_first(base);
+                    if (base >= r_end) {
+                        drained = true;
                         continue;
                     }
                     q_next = base;
-                    q_end = min(base + static_cast<unsigned long long>(chunk), s1);
+                    q_end = min(base + static_cast<unsigned long long>(chunk), r_end);
                 }
                 const unsigned rank = lane_rank(idle);
                 const unsigned long long avail = q_end - q_next;
@@ -204,10 +204,10 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                     if (go) {
                         jb = j;
                         pix = p;
-                        if constexpr (BATCH) {
-                            P = orbit_params(J);
-                            if constexpr (VAR == kVarMixed) orb.set_kind(P);
-                        }
+                        if constexpr (BATCH) P = orbit_params(J);
+                        clamp = J.clamp;
+                        max_steps = J.max_steps;
+                        refine_iters = J.refine_iters;
                         t = lo;
                         t1 = hi;
                         steps = 0;
@@ -216,6 +216,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                         bodies = 0;
                         phase = entry >= 0 ? kCut : kMarch;
                         orb.init(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz));
+                        live = true;
                     }
                 }
                 q_next += min(static_cast<unsigned long long>(__popcll(idle)), avail);
@@ -226,17 +227,20 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
         // -------------------------------------------------- orbit bodies
         // Iterate while at least `orbit_lanes` lanes still iterate (and at
         // least once); lanes whose orbit ends wait for the step below, the
-        // stragglers carry their orbit state into the next trip.
-        for (int b = 0; b < kMaxBodiesPerTrip; ++b) {
-            const bool iter = (phase == kCut || phase == kMarch || phase == kRefine) && !orb.done(P);
-            const int n_iter = __popcll(__ballot(iter));
-            if (n_iter == 0 || (b > 0 && n_iter < orbit_lanes)) break;
-            if (iter) orb.body(P);
+        // stragglers carry their orbit state into the next trip.  `live` is
+        // a lane mask, so a body costs its arithmetic plus the bailout and
+        // iteration-limit compares.
+        {
+            unsigned long long act = __ballot(live);
+            for (int b = 0; act != 0ull && b < kMaxBodiesPerTrip; ++b) {
+                if (b > 0 && __popcll(act) < orbit_lanes) break;
+                if (live) live = orb.body(P) && orb.k < P.max_iter;
+                act = __ballot(live);
+            }
         }
-        if (phase == kCut || phase == kMarch || phase == kRefine) {
-            if (orb.done(P)) {
-                const JobDev& J = job_ref<BATCH>(jobs, job1, jb);
-                const DEResult de = orb.result();
+        if (!live && (phase == kCut || phase == kMarch || phase == kRefine)) {
+            {
+                const DEResult de = orb.result(P);
                 evals += 1u;
                 bodies += static_cast<unsigned>(de.bodies);
                 const float d = de.d;
@@ -266,7 +270,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                             gb = d - fmaf(er, t, ea);
                             t1 = t;
                             rk = 0;
-                            if (J.refine_iters > 0 && t1 - lt > kRefineTol * fmaf(er, t1, ea)) {
+                            if (refine_iters > 0 && t1 - lt > kRefineTol * fmaf(er, t1, ea)) {
                                 phase = kRefine;
                                 t = 0.5f * (lt + t1);
                             } else {
@@ -280,11 +284,11 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                     } else {
                         lt = t;
                         lh = d;
-                        t += fminf(d, J.clamp);
+                        t += fminf(d, clamp);
                         if (t > t1) {
                             status = SHADOW ? 0 : kMissTmax;
                             phase = kDone;
-                        } else if (steps >= J.max_steps) {
+                        } else if (steps >= max_steps) {
                             status = SHADOW ? kFlagShadowed : (kHitExhausted | kFlagUnrefined);
                             phase = kDone;
                         }
@@ -294,15 +298,17 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                     const float fx = d - fmaf(er, t, ea);
                     if (fx < 0.0f) { t1 = t; gb = fx; } else { lt = t; lh = fx; }
                     ++rk;
-                    if (rk >= J.refine_iters || t1 - lt <= kRefineTol * fmaf(er, t1, ea)) {
+                    if (rk >= refine_iters || t1 - lt <= kRefineTol * fmaf(er, t1, ea)) {
                         t = fmaf(-gb, (t1 - lt) / (gb - lh), t1);   // secant on the final bracket
                         phase = kDone;
                     } else {
                         t = 0.5f * (lt + t1);
                     }
                 }
-                if (phase == kCut || phase == kMarch || phase == kRefine)
+                if (phase == kCut || phase == kMarch || phase == kRefine) {
                     orb.init(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz));
+                    live = true;
+                }
             }
         }
     }
@@ -320,14 +326,15 @@ __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ 
                                                      WorkspaceHeader* __restrict__ hdr) {
     using Orbit = typename OrbitOf<VAR>::T;
     int n_jobs = 1;
-    unsigned long long total_rays = static_cast<unsigned long long>(job1.ray_count);
+    unsigned long long r_begin = 0, r_end = static_cast<unsigned long long>(job1.ray_count);
     if constexpr (BATCH) {
         n_jobs = hdr->n_jobs;
-        total_rays = hdr->total_rays;
+        r_begin = hdr->range[VAR][0];
+        r_end = hdr->range[VAR][1];
     }
     const unsigned long long stride = static_cast<unsigned long long>(gridDim.x) * blockDim.x;
-    for (unsigned long long g = static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-         g < total_rays; g += stride) {
+    for (unsigned long long g = r_begin + static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+         g < r_end; g += stride) {
         int j, px, py;
         if (!ray_pixel<BATCH>(jobs, job1, n_jobs, static_cast<long long>(g), j, px, py)) continue;
         const JobDev& J = job_ref<BATCH>(jobs, job1, j);
@@ -344,7 +351,6 @@ __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ 
         } else {
             const OrbitParams P = orbit_params(J);
             Orbit orb;
-            if constexpr (VAR == kVarMixed) orb.set_kind(P);
             float dx, dy, dz;
             primary_dir(J, px, py, dx, dy, dz);
             const float ts = J.depth[p];
@@ -405,34 +411,39 @@ __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ 
 }
 
 __global__ void reset_queue_kernel(WorkspaceHeader* hdr) {
-    if (threadIdx.x < 2 * kQueues) hdr->queue[threadIdx.x / kQueues][threadIdx.x % kQueues] = 0ull;
+    if (threadIdx.x < 2 * kNumVariants) hdr->queue[threadIdx.x >> 1][threadIdx.x & 1] = 0ull;
 }
 
 static hipError_t mark(hipEvent_t* marks, int k, hipStream_t stream) {
     return marks ? hipEventRecord(marks[k], stream) : hipSuccess;
 }
 
+// One stage (0 primary march, 1 normals, 2 shadow march) of one group.
 template <int VAR, bool BATCH>
-static hipError_t launch_var(const LaunchCfg& cfg, const JobDev* jobs, const JobDev& job1, WorkspaceHeader* hdr,
-                             bool any_shadow, hipStream_t stream, hipEvent_t* marks) {
-    hipError_t e = mark(marks, 0, stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((march_kernel<VAR, BATCH, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, jobs, job1,
-                       hdr, cfg.chunk, cfg.orbit_lanes, cfg.rare_lanes);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = mark(marks, 1, stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((normal_kernel<VAR, BATCH>), dim3(cfg.normal_grid), dim3(256), 0, stream, jobs, job1, hdr);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = mark(marks, 2, stream);
-    if (e != hipSuccess) return e;
-    if (any_shadow) {
-        hipLaunchKernelGGL((march_kernel<VAR, BATCH, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, jobs, job1,
-                           hdr, cfg.chunk, cfg.orbit_lanes, cfg.rare_lanes);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+static hipError_t launch_stage(int stage, const LaunchCfg& cfg, const JobDev* jobs, const JobDev& job1,
+                               WorkspaceHeader* hdr, hipStream_t stream) {
+    if (stage == 0) {
+        hipLaunchKernelGGL((march_kernel<VAR, BATCH, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, jobs,
+                           job1, hdr, cfg.chunk, cfg.orbit_lanes, cfg.rare_lanes);
+    } else if (stage == 1) {
+        hipLaunchKernelGGL((normal_kernel<VAR, BATCH>), dim3(cfg.normal_grid), dim3(256), 0, stream, jobs, job1,
+                           hdr);
+    } else {
+        hipLaunchKernelGGL((march_kernel<VAR, BATCH, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, jobs,
+                           job1, hdr, cfg.chunk, cfg.orbit_lanes, cfg.rare_lanes);
     }
-    return mark(marks, 3, stream);
+    return hipGetLastError();
+}
+
+template <bool BATCH>
+static hipError_t launch_stage_var(int variant, int stage, const LaunchCfg& cfg, const JobDev* jobs,
+                                   const JobDev& job1, WorkspaceHeader* hdr, hipStream_t stream) {
+    switch (variant) {
+        case kVarJulia: return launch_stage<kVarJulia, BATCH>(stage, cfg, jobs, job1, hdr, stream);
+        case kVarBulbReal: return launch_stage<kVarBulbReal, BATCH>(stage, cfg, jobs, job1, hdr, stream);
+        case kVarBulbInt: return launch_stage<kVarBulbInt, BATCH>(stage, cfg, jobs, job1, hdr, stream);
+        default: return launch_stage<kVarBulb8, BATCH>(stage, cfg, jobs, job1, hdr, stream);
+    }
 }
 
 template <int VAR, bool BATCH>
@@ -445,33 +456,24 @@ const void* trace_kernel_symbol(int variant, bool batch) {
         case kVarJulia: return batch ? kernel_ptr<kVarJulia, true>() : kernel_ptr<kVarJulia, false>();
         case kVarBulbReal: return batch ? kernel_ptr<kVarBulbReal, true>() : kernel_ptr<kVarBulbReal, false>();
         case kVarBulbInt: return batch ? kernel_ptr<kVarBulbInt, true>() : kernel_ptr<kVarBulbInt, false>();
-        case kVarBulb8: return batch ? kernel_ptr<kVarBulb8, true>() : kernel_ptr<kVarBulb8, false>();
-        default: return batch ? kernel_ptr<kVarMixed, true>() : kernel_ptr<kVarMixed, false>();
+        default: return batch ? kernel_ptr<kVarBulb8, true>() : kernel_ptr<kVarBulb8, false>();
     }
 }
 
-hipError_t launch_trace(int variant, bool batch, const LaunchCfg& cfg, const JobDev* jobs, const JobDev& job1,
-                        WorkspaceHeader* hdr, bool any_shadow, hipStream_t stream, hipEvent_t* marks) {
+hipError_t launch_trace(const TraceGroup* groups, int n_groups, bool batch, const JobDev* jobs, const JobDev& job1,
+                        WorkspaceHeader* hdr, hipStream_t stream, hipEvent_t* marks) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, stream, hdr);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    switch (variant) {
-        case kVarJulia:
-            return batch ? launch_var<kVarJulia, true>(cfg, jobs, job1, hdr, any_shadow, stream, marks)
-                         : launch_var<kVarJulia, false>(cfg, jobs, job1, hdr, any_shadow, stream, marks);
-        case kVarBulbReal:
-            return batch ? launch_var<kVarBulbReal, true>(cfg, jobs, job1, hdr, any_shadow, stream, marks)
-                         : launch_var<kVarBulbReal, false>(cfg, jobs, job1, hdr, any_shadow, stream, marks);
-        case kVarBulbInt:
-            return batch ? launch_var<kVarBulbInt, true>(cfg, jobs, job1, hdr, any_shadow, stream, marks)
-                         : launch_var<kVarBulbInt, false>(cfg, jobs, job1, hdr, any_shadow, stream, marks);
-        case kVarBulb8:
-            return batch ? launch_var<kVarBulb8, true>(cfg, jobs, job1, hdr, any_shadow, stream, marks)
-                         : launch_var<kVarBulb8, false>(cfg, jobs, job1, hdr, any_shadow, stream, marks);
-        default:
-            return batch ? launch_var<kVarMixed, true>(cfg, jobs, job1, hdr, any_shadow, stream, marks)
-                         : launch_var<kVarMixed, false>(cfg, jobs, job1, hdr, any_shadow, stream, marks);
+    for (int stage = 0; stage < 3 && e == hipSuccess; ++stage) {
+        e = mark(marks, stage, stream);
+        for (int g = 0; g < n_groups && e == hipSuccess; ++g) {
+            if (stage == 2 && !groups[g].any_shadow) continue;
+            e = batch ? launch_stage_var<true>(groups[g].variant, stage, groups[g].cfg, jobs, job1, hdr, stream)
+                      : launch_stage_var<false>(groups[g].variant, stage, groups[g].cfg, jobs, job1, hdr, stream);
+        }
     }
+    if (e == hipSuccess) e = mark(marks, 3, stream);
+    return e;
 }
 
 }  // namespace frt
