@@ -37,7 +37,8 @@
  *                          face, 4 hit by running out of steps;
  *                          bit 3: shadowed (the shadow ray hit);
  *                          bit 4: depth not refined (first sample or
- *                          running out of steps)
+ *                          running out of steps);
+ *                          bit 6: a shadow ray was traced from this hit
  *   counters uint32[8][P]  optional (NULL to skip), per pixel:
  *                          0 primary march samples,
  *                          1 distance evaluations of the primary ray (cut

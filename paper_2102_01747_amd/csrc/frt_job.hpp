@@ -28,6 +28,7 @@ enum : uint8_t {
     kHitExhausted = 4,
     kFlagShadowed = 8,
     kFlagUnrefined = 16,
+    kFlagShadowRay = 64,   // set by the normal kernel on hits that cast a shadow ray
 };
 
 constexpr int kCounterPlanes = 8;      // optional per-pixel work counters

@@ -69,6 +69,11 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
     }
     unsigned long long q_next = 0, q_end = 0;   // wave-uniform window of claimed rays
     bool drained = false;
+    // shadow rays: the current tile's first ray index and the mask of its
+    // shadow-casting pixels not yet handed to a lane (wave-uniform)
+    unsigned long long tile_g = 0, tmask = 0;
+    __shared__ uint8_t slots[8][64];   // per wave: lane index of the k-th set bit of tmask
+    uint8_t* slot = slots[threadIdx.x >> 6];
 
     int phase = kIdle;
     int jb = 0, pix = 0, entry = -1, status = 0, steps = 0, rk = 0, hit_it = 0;
@@ -86,8 +91,9 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
         // ------------------------------------------ finished rays + refill
         const unsigned long long m_busy = __ballot(phase == kCut || phase == kMarch || phase == kRefine);
         const unsigned long long m_done = __ballot(phase == kDone);
-        if (m_busy == 0ull && m_done == 0ull && drained) break;
-        const int waiting = __popcll(m_done) + (drained ? 0 : __popcll(__ballot(phase == kIdle)));
+        const bool exhausted = drained && tmask == 0ull;
+        if (m_busy == 0ull && m_done == 0ull && exhausted) break;
+        const int waiting = __popcll(m_done) + (exhausted ? 0 : __popcll(__ballot(phase == kIdle)));
         if (m_busy == 0ull || waiting >= rare_lanes) {
             if (phase == kDone) {
                 const JobDev& J = job_ref<BATCH>(jobs, job1, jb);
@@ -134,6 +140,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
             }
 
             unsigned long long idle = __ballot(phase == kIdle);
+            if constexpr (!SHADOW) {
             while (idle != 0ull && !drained) {
                 if (q_next >= q_end) {
                     unsigned long long base = 0;
@@ -155,7 +162,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                     const int p = py * J.width + px;
                     float lo, hi;
                     bool go = false;
-                    if constexpr (!SHADOW) {
+                    {
                         primary_dir(J, px, py, dx, dy, dz);
                         ox = J.eye[0];
                         oy = J.eye[1];
@@ -179,27 +186,6 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                                 for (int k = 0; k < kCounterPlanes; ++k) J.counters[k * NP + p] = 0u;
                             }
                         }
-                    } else if (J.shadow && (J.status[p] & 7) >= kHit) {
-                        const long long NP = J.npix;
-                        const float nx = J.normal[p], ny = J.normal[NP + p], nz = J.normal[2 * NP + p];
-                        const float ndl = fmaf(nx, J.light[0], fmaf(ny, J.light[1], nz * J.light[2]));
-                        if (ndl > 0.0f) {
-                            float pdx, pdy, pdz;
-                            primary_dir(J, px, py, pdx, pdy, pdz);
-                            const float ts = J.depth[p];
-                            const float eps = fmaf(J.eps_rel, ts, J.eps_abs);
-                            const float off = 4.0f * eps;
-                            ox = fmaf(off, nx, fmaf(ts, pdx, J.eye[0]));
-                            oy = fmaf(off, ny, fmaf(ts, pdy, J.eye[1]));
-                            oz = fmaf(off, nz, fmaf(ts, pdz, J.eye[2]));
-                            dx = J.light[0];
-                            dy = J.light[1];
-                            dz = J.light[2];
-                            ea = eps;
-                            er = 0.0f;
-                            status = 0;
-                            go = ray_interval(J, ox, oy, oz, dx, dy, dz, eps, lo, hi, entry);
-                        }
                     }
                     if (go) {
                         jb = j;
@@ -221,6 +207,94 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                 }
                 q_next += min(static_cast<unsigned long long>(__popcll(idle)), avail);
                 idle = __ballot(phase == kIdle);
+            }
+            } else {
+            // Shadow rays: claim 64-ray tiles and read the tile's status bytes
+            // once (one load per lane); the normal kernel flagged the pixels
+            // that cast a shadow ray, so the tile's rays reduce to a 64-bit
+            // mask and the idle lanes take its set bits in order, through
+            // this wave's slot table in LDS.
+            while (idle != 0ull && (tmask != 0ull || !drained)) {
+                if (tmask == 0ull) {
+                    if (q_next >= q_end) {
+                        unsigned long long base = 0;
+                        if (__lane_id() == 0) base = atomicAdd(queue, static_cast<unsigned long long>(chunk));
+                        base = r_begin + bcast_first(base);
+                        if (base >= r_end) {
+                            drained = true;
+                            break;
+                        }
+                        q_next = base;
+                        q_end = min(base + static_cast<unsigned long long>(chunk), r_end);
+                    }
+                    tile_g = q_next;
+                    q_next += 64ull;
+                    int j, px, py;
+                    bool cast = false;
+                    if (ray_pixel<BATCH>(jobs, job1, n_jobs, static_cast<long long>(tile_g + __lane_id()), j, px,
+                                         py)) {
+                        const JobDev& J = job_ref<BATCH>(jobs, job1, j);
+                        cast = (J.status[py * J.width + px] & kFlagShadowRay) != 0;
+                    }
+                    tmask = __ballot(cast);
+                    continue;
+                }
+                const unsigned lane = __lane_id();
+                if ((tmask >> lane) & 1ull) slot[lane_rank(tmask)] = static_cast<uint8_t>(lane);
+                __builtin_amdgcn_wave_barrier();
+                const unsigned nbits = static_cast<unsigned>(__popcll(tmask));
+                const unsigned nidle = static_cast<unsigned>(__popcll(idle));
+                const unsigned rank = lane_rank(idle);
+                if (phase == kIdle && rank < nbits) {
+                    int j, px, py;
+                    ray_pixel<BATCH>(jobs, job1, n_jobs, static_cast<long long>(tile_g + slot[rank]), j, px, py);
+                    const JobDev& J = job_ref<BATCH>(jobs, job1, j);
+                    const int p = py * J.width + px;
+                    const long long NP = J.npix;
+                    const float nx = J.normal[p], ny = J.normal[NP + p], nz = J.normal[2 * NP + p];
+                    float pdx, pdy, pdz;
+                    primary_dir(J, px, py, pdx, pdy, pdz);
+                    const float ts = J.depth[p];
+                    const float eps = fmaf(J.eps_rel, ts, J.eps_abs);
+                    const float off = 4.0f * eps;
+                    ox = fmaf(off, nx, fmaf(ts, pdx, J.eye[0]));
+                    oy = fmaf(off, ny, fmaf(ts, pdy, J.eye[1]));
+                    oz = fmaf(off, nz, fmaf(ts, pdz, J.eye[2]));
+                    dx = J.light[0];
+                    dy = J.light[1];
+                    dz = J.light[2];
+                    ea = eps;
+                    er = 0.0f;
+                    status = 0;
+                    float lo, hi;
+                    if (ray_interval(J, ox, oy, oz, dx, dy, dz, eps, lo, hi, entry)) {
+                        jb = j;
+                        pix = p;
+                        if constexpr (BATCH) P = orbit_params(J);
+                        clamp = J.clamp;
+                        max_steps = J.max_steps;
+                        refine_iters = J.refine_iters;
+                        t = lo;
+                        t1 = hi;
+                        steps = 0;
+                        hit_it = 0;
+                        evals = 0;
+                        bodies = 0;
+                        phase = entry >= 0 ? kCut : kMarch;
+                        orb.init(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz));
+                        live = true;
+                    }
+                }
+                // keep the bits not handed out: from the nidle-th set bit on
+                if (nidle >= nbits) {
+                    tmask = 0ull;
+                } else {
+                    const unsigned cut = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(slot[nidle]));
+                    tmask &= ~((1ull << cut) - 1ull);
+                }
+                __builtin_amdgcn_wave_barrier();
+                idle = __ballot(phase == kIdle);
+            }
             }
         }
 
@@ -399,6 +473,7 @@ __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ 
             J.normal[2 * NP + p] = nz;
         }
         const float ndl = fmaf(nx, J.light[0], fmaf(ny, J.light[1], nz * J.light[2]));
+        if (J.shadow && ndl > 0.0f) J.status[p] = static_cast<uint8_t>(J.status[p] | kFlagShadowRay);
         const float lam = fmaf(J.k_d, fmaxf(ndl, 0.0f), J.k_a);
         J.colour[p] = J.albedo[0] * lam;
         J.colour[NP + p] = J.albedo[1] * lam;
