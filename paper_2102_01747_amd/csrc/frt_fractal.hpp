@@ -11,8 +11,13 @@
 // bodies per trip and let lanes whose orbit has ended move on to their next
 // sample without waiting for the slowest lane of the wave.  body() returns
 // whether the orbit is still within the bailout; the caller stops a lane when
-// it returns false or after max_iter bodies (k counts the bodies run), so the
-// hot loop carries no per-lane escape flag.
+// it returns false or after max_iter bodies (k counts the bodies run).
+// step(P, live) is the same body for a loop that runs whole waves with no
+// per-lane branch: `live` is the wave's mask of iterating lanes, every lane
+// computes the body, and only the values the estimate reads (|z|^2, the
+// derivative and k) are kept in live lanes -- a stopped lane's other
+// coordinates run on unused until its next init.  It returns the mask of
+// lanes still iterating.
 #pragma once
 
 #include "frt_math.hpp"
@@ -71,6 +76,23 @@ struct JuliaOrbit {
         ++k;
         return !(m2 > P.bail2);
     }
+    __device__ __forceinline__ unsigned long long step(const OrbitParams& P, unsigned long long live_mask) {
+        const bool live = __builtin_amdgcn_inverse_ballot_w64(live_mask);
+        const float pn = prod * m2;
+        const float vv = fmaf(b, b, fmaf(e, e, w * w));
+        const float a2 = a + a;
+        const float na = fmaf(a, a, -vv) + P.c0;
+        b = fmaf(a2, b, P.c1);
+        e = fmaf(a2, e, P.c2);
+        w = fmaf(a2, w, P.c3);
+        a = na;
+        const float mn = fmaf(a, a, fmaf(b, b, fmaf(e, e, w * w)));
+        const int kn = k + 1;
+        prod = live ? pn : prod;
+        m2 = live ? mn : m2;
+        k = live ? kn : k;
+        return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2) && kn < P.max_iter);
+    }
     __device__ __forceinline__ DEResult result(const OrbitParams& P) const {
         DEResult r;
         const bool esc = m2 > P.bail2;
@@ -107,6 +129,59 @@ struct BulbOrbit {
         m = fmaf(x, x, fmaf(y, y, z * z));
         dr = 1.0f;
         k = 0;
+    }
+    // one body from (w, m, dr): the new point and derivative
+    __device__ __forceinline__ void map(const OrbitParams& P, float& nx, float& ny, float& nz, float& ndr) const {
+        if constexpr (MODE == 0) {
+            const float rn1 = hw_exp2(P.nm1_half * hw_log2(m));
+            ndr = fmaf(P.n * rn1, dr, 1.0f);
+            const float rinv = m > 0.0f ? hw_rsq(m) : 0.0f;
+            const float r = m * rinv;
+            const float u = fminf(fmaxf(wy * rinv, -1.0f), 1.0f);
+            const float bt = fast_acos(u) * P.n_rev;
+            const float at = fast_atan2(wx, wz) * P.n_rev;
+            const float rn = rn1 * r;
+            const float rsb = rn * hw_sin_rev(bt);
+            ny = fmaf(rn, hw_cos_rev(bt), py);
+            nx = fmaf(rsb, hw_sin_rev(at), px);
+            nz = fmaf(rsb, hw_cos_rev(at), pz);
+        } else {
+            const float rho2 = fmaxf(fmaf(wx, wx, wz * wz), kTinyFloor);
+            const float irho = hw_rsq(rho2);
+            float yr = wy, yi = rho2 * irho;
+            float zr = wz * irho, zi = wx * irho;
+            if constexpr (MODE > 0) {
+                if constexpr ((MODE & 1) == 0) {
+                    const float rinv = hw_rsq(fmaxf(m, kTinyFloor));
+                    ndr = fmaf(static_cast<float>(MODE) * (ipow_c<MODE / 2>(m) * rinv), dr, 1.0f);
+                } else {
+                    ndr = fmaf(static_cast<float>(MODE) * ipow_c<(MODE - 1) / 2>(m), dr, 1.0f);
+                }
+                cpow_c<MODE>(yr, yi);
+                cpow_c<MODE>(zr, zi);
+            } else {
+                const float rinv = hw_rsq(fmaxf(m, kTinyFloor));
+                const float r = m * rinv;
+                ndr = fmaf(P.n * ipow(r, P.ipow - 1), dr, 1.0f);
+                cpow_int(yr, yi, P.ipow);
+                cpow_int(zr, zi, P.ipow);
+            }
+            nx = fmaf(yi, zi, px);
+            ny = yr + py;
+            nz = fmaf(yi, zr, pz);
+        }
+    }
+    __device__ __forceinline__ unsigned long long step(const OrbitParams& P, unsigned long long live_mask) {
+        const bool live = __builtin_amdgcn_inverse_ballot_w64(live_mask);
+        float nx, ny, nz, ndr;
+        map(P, nx, ny, nz, ndr);
+        wx = nx; wy = ny; wz = nz;
+        const float mn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+        const int kn = k + 1;
+        dr = live ? ndr : dr;
+        m = live ? mn : m;
+        k = live ? kn : k;
+        return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2) && kn < P.max_iter);
     }
     __device__ __forceinline__ bool body(const OrbitParams& P) {
         if constexpr (MODE == 0) {

@@ -83,7 +83,11 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
     // march settings of the lane's job, copied when the ray is claimed
     float clamp = 0.2f;
     int max_steps = 1, refine_iters = 0;
-    bool live = false;   // the lane's orbit is still iterating
+    // lanes whose orbit is still iterating, as a wave-uniform mask (the orbit
+    // loop then needs one ballot and one scalar AND a body); lanes (re)started
+    // in divergent code set `rearm`, folded into the mask at uniform points
+    unsigned long long live = 0ull;
+    bool rearm = false;
     OrbitParams P = orbit_params(job1);
     Orbit orb;
 
@@ -202,7 +206,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                         bodies = 0;
                         phase = entry >= 0 ? kCut : kMarch;
                         orb.init(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz));
-                        live = true;
+                        rearm = true;
                     }
                 }
                 q_next += min(static_cast<unsigned long long>(__popcll(idle)), avail);
@@ -282,7 +286,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                         bodies = 0;
                         phase = entry >= 0 ? kCut : kMarch;
                         orb.init(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz));
-                        live = true;
+                        rearm = true;
                     }
                 }
                 // keep the bits not handed out: from the nidle-th set bit on
@@ -301,18 +305,19 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
         // -------------------------------------------------- orbit bodies
         // Iterate while at least `orbit_lanes` lanes still iterate (and at
         // least once); lanes whose orbit ends wait for the step below, the
-        // stragglers carry their orbit state into the next trip.  `live` is
-        // a lane mask, so a body costs its arithmetic plus the bailout and
-        // iteration-limit compares.
-        {
-            unsigned long long act = __ballot(live);
-            for (int b = 0; act != 0ull && b < kMaxBodiesPerTrip; ++b) {
-                if (b > 0 && __popcll(act) < orbit_lanes) break;
-                if (live) live = orb.body(P) && orb.k < P.max_iter;
-                act = __ballot(live);
-            }
+        // stragglers carry their orbit state into the next trip.  The body
+        // runs on every lane with no branch; step() keeps the estimate's
+        // inputs only in live lanes (three selects and two compares a body).
+        live |= __ballot(rearm);
+        rearm = false;
+        if (live != 0ull) {
+            const int keep = max(orbit_lanes, 1);
+            int b = 0;
+            do {
+                live = orb.step(P, live);
+            } while (++b < kMaxBodiesPerTrip && __popcll(live) >= keep);
         }
-        if (!live && (phase == kCut || phase == kMarch || phase == kRefine)) {
+        if (!__builtin_amdgcn_inverse_ballot_w64(live) && (phase == kCut || phase == kMarch || phase == kRefine)) {
             {
                 const DEResult de = orb.result(P);
                 evals += 1u;
@@ -381,10 +386,12 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                 }
                 if (phase == kCut || phase == kMarch || phase == kRefine) {
                     orb.init(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz));
-                    live = true;
+                    rearm = true;
                 }
             }
         }
+        live |= __ballot(rearm);
+        rearm = false;
     }
 }
 
