@@ -361,8 +361,10 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                             phase = kDone;
                         }
                     } else {
-                        lt = t;
-                        lh = d;
+                        if constexpr (!SHADOW) {
+                            lt = t;
+                            lh = d;
+                        }
                         t += fminf(d, clamp);
                         if (t > t1) {
                             status = SHADOW ? 0 : kMissTmax;
@@ -372,7 +374,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                             phase = kDone;
                         }
                     }
-                } else if (phase == kRefine) {
+                } else if (!SHADOW && phase == kRefine) {   // shadow rays stop at their first hit
                     // bisection step on [lt, t1]; t is the midpoint just evaluated
                     const float fx = d - fmaf(er, t, ea);
                     if (fx < 0.0f) { t1 = t; gb = fx; } else { lt = t; lh = fx; }
