@@ -73,14 +73,17 @@ def time_config(jobs, frames, ws, batch, reps=5, device="cuda"):
     return statistics.median(times)
 
 
-def tune(jobs, batch=True, reps=5, passes=2, device="cuda", log=None):
-    """Coordinate descent over SPACE for every variant the jobs use (each
-    timed on the whole batch, the others held at their current setting);
-    installs the best settings and returns them per variant with the time."""
+def tune(jobs, batch=True, reps=5, passes=2, device="cuda", log=None, variants=None):
+    """Coordinate descent over SPACE for every variant the jobs use (or the
+    given subset; each timed on the whole batch, the others held at their
+    current setting); installs the best settings and returns them per
+    variant with the time."""
     frames = [alloc_frame(j, device) for j in jobs]
     ws = alloc_workspace(len(jobs), device)
     results = []
     for var in variants_of(jobs):
+        if variants is not None and var not in variants:
+            continue
         cur = dict(zip(KEYS, autotune_get(var)))
         timed = {}
 
@@ -145,10 +148,13 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--out", default=TUNED_PATH)
+    ap.add_argument("--variants", nargs="*", default=None,
+                    help="tune only these kernel variants (default: every variant the workload uses)")
     args = ap.parse_args()
     jobs = {"bulb_views": W.bulb_views, "julia_batch": W.julia_batch,
             "diff_set": lambda: W.diff_set()[0], "stress": W.stress_sweep}[args.workload]()
-    for res in tune(jobs, batch=True, reps=args.reps, passes=args.passes, log=lambda m: print(m, flush=True)):
+    for res in tune(jobs, batch=True, reps=args.reps, passes=args.passes, log=lambda m: print(m, flush=True),
+                    variants=args.variants):
         print(json.dumps(res), flush=True)
         save_tuned(res, args.workload, args.out)
 

@@ -353,7 +353,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                                 phase = kRefine;
                                 t = 0.5f * (lt + t1);
                             } else {
-                                t = fmaf(-gb, (t1 - lt) / (gb - lh), t1);   // secant on the bracket
+                                t = fmaf(-gb, __fdividef(t1 - lt, gb - lh), t1);   // secant on the bracket
                                 phase = kDone;
                             }
                         } else {
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                     if (fx < 0.0f) { t1 = t; gb = fx; } else { lt = t; lh = fx; }
                     ++rk;
                     if (rk >= refine_iters || t1 - lt <= kRefineTol * fmaf(er, t1, ea)) {
-                        t = fmaf(-gb, (t1 - lt) / (gb - lh), t1);   // secant on the final bracket
+                        t = fmaf(-gb, __fdividef(t1 - lt, gb - lh), t1);   // secant on the final bracket
                         phase = kDone;
                     } else {
                         t = 0.5f * (lt + t1);
