@@ -1,6 +1,6 @@
 /*
  * frt_oracle.c -- FP64 CPU oracle for per-pixel sphere tracing of escape-time
- * fractals: the quaternion Julia set z^2+c sliced to 3-D (optionally cut by
+ * fractals: the quaternion Julia set z^p+c sliced to 3-D (optionally cut by
  * planes) and the White-Nylander power-n Mandelbulb, as described in
  * da Silva, Novello, Lopes, Velho, "Real-time rendering of complex fractals"
  * (arXiv 2102.01747).
@@ -16,8 +16,11 @@
  * widened to double, so parameter rounding does not pollute parity.
  *
  * Readings of the paper that this file fixes (each one repeated at its use):
- *   R1  Julia degree 2 (the text's z^2+c), running squared derivative
- *       dz2 <- 4|z|^2 dz2 (Eq. 3-4 with p=2), updated before z.
+ *   R1  Julia degree p, an integer >= 2 (2 is the text's z^2+c, 3 the cubic
+ *       of Listing 4).  z^p is p - 1 quaternion products of z by itself.
+ *       Running squared derivative dz2 <- p^2 |z^(p-1)|^2 dz2 (Eq. 4 taken
+ *       in norm, as Listing 4 does with 9 |z^2|^2 at p = 3), updated before
+ *       z.
  *   R2  Quaternion component 0 is the real part; the 3-D slice is z0=(x,y,z,0).
  *   R3  DE d = 0.25 ln(m2) sqrt(m2/dz2) = 0.5|z|ln|z|/|z'| (Listings 4, 7).
  *   R4  Mandelbulb power map as in Listing 7 (y is the polar axis,
@@ -57,9 +60,10 @@ typedef struct {
 } or_camera;
 
 typedef struct {
-    int32_t kind;      /* 0 = quaternion Julia z^2+c, 1 = Mandelbulb p^n+c */
+    int32_t kind;      /* 0 = quaternion Julia z^p+c, 1 = Mandelbulb p^n+c */
     double c[4];       /* Julia constant (component 0 real)                 */
-    double power;      /* Mandelbulb exponent n (real, >= 2)                */
+    double power;      /* Mandelbulb exponent n (real, >= 2); Julia degree  */
+                       /* p (an integer >= 2)                               */
     int32_t max_iter;  /* orbit bodies per distance evaluation (>= 1)       */
     double bailout2;   /* escape when |z|^2 exceeds this                    */
     double bound_radius; /* caller's bounding radius; the larger of it and   */
@@ -114,6 +118,46 @@ void oracle_quat_square(const double z[4], double out[4]) {
     out[3] = 2.0 * a * z[3];
 }
 
+/* Hamilton product x y with i^2 = j^2 = k^2 = ijk = -1:                     */
+/*   (a1 + v1)(a2 + v2) = a1 a2 - v1.v2 + a1 v2 + a2 v1 + v1 x v2.           */
+void oracle_quat_mul(const double x[4], const double y[4], double out[4]) {
+    double r0 = x[0] * y[0] - (x[1] * y[1] + x[2] * y[2] + x[3] * y[3]);
+    double r1 = x[0] * y[1] + y[0] * x[1] + (x[2] * y[3] - x[3] * y[2]);
+    double r2 = x[0] * y[2] + y[0] * x[2] + (x[3] * y[1] - x[1] * y[3]);
+    double r3 = x[0] * y[3] + y[0] * x[3] + (x[1] * y[2] - x[2] * y[1]);
+    out[0] = r0; out[1] = r1; out[2] = r2; out[3] = r3;
+}
+
+/* z^p for an integer p >= 1 (R1): z^1 = z, z^2 by the square above, and    */
+/* each further power one more product by z.                                 */
+void oracle_quat_pow(const double z[4], int32_t p, double out[4]) {
+    double w[4] = { z[0], z[1], z[2], z[3] };
+    if (p >= 2) oracle_quat_square(z, w);
+    for (int32_t k = 3; k <= p; ++k) {
+        double t[4];
+        oracle_quat_mul(w, z, t);
+        for (int i = 0; i < 4; ++i) w[i] = t[i];
+    }
+    for (int i = 0; i < 4; ++i) out[i] = w[i];
+}
+
+static double qlen2(const double z[4]) {
+    return z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3];
+}
+
+/* Julia degree (R1). */
+static int32_t julia_degree(const or_fractal* f) {
+    return (int32_t)f->power;
+}
+
+/* Factor the squared running derivative gains in one body at z (R1):       */
+/* p^2 |z^(p-1)|^2, which is 4 |z|^2 at p = 2.                               */
+static double julia_deriv_factor(const double z[4], int32_t p) {
+    double zp[4];
+    oracle_quat_pow(z, p - 1, zp);
+    return (double)p * (double)p * qlen2(zp);
+}
+
 /* ------------------------------------------------------------------------ */
 /* White-Nylander n-th power, Eq. 1 in the axis convention of Listing 7      */
 /* (R4): y is the polar axis, theta = acos(y/r), phi = atan2(x, z),          */
@@ -136,9 +180,10 @@ void oracle_bulb_power(const double w[3], double n, double out[3]) {
 
 /* ------------------------------------------------------------------------ */
 /* Distance estimators.                                                      */
-/* Julia (Sec. 2, Eq. 2-4; Listing 4 at degree 2, R1-R3, R5):                */
-/*   z = (p, 0); dz2 = 1; repeat max_iter: dz2 *= 4|z|^2; z = z^2 + c;       */
-/*   m2 = |z|^2; stop if m2 > bailout2.  d = 0.25 ln(m2) sqrt(m2 / dz2).     */
+/* Julia (Sec. 2, Eq. 2-4; Listing 4, R1-R3, R5), degree p:                  */
+/*   z = (x, 0); dz2 = 1; repeat max_iter: dz2 *= p^2 |z^(p-1)|^2;           */
+/*   z = z^p + c; m2 = |z|^2; stop if m2 > bailout2.                         */
+/*   d = 0.25 ln(m2) sqrt(m2 / dz2).                                          */
 /* Mandelbulb (Listing 7 with general n, R4-R5): w = p; m = |w|^2; dr = 1;   */
 /*   repeat: dr = n r^(n-1) dr + 1 (r = |w| before the update);              */
 /*   w = w^n + p; m = |w|^2; stop if m > bailout2.  d = 0.25 ln(m) sqrt(m)/dr.*/
@@ -151,13 +196,14 @@ static de_result julia_de(const or_fractal* f, const double p[3]) {
     double z[4] = { p[0], p[1], p[2], 0.0 };
     double dz2 = 1.0, m2 = 0.0;
     int32_t n = 0, bodies = 0;
+    int32_t deg = julia_degree(f);
     for (int32_t i = 0; i < f->max_iter; ++i) {
         ++bodies;
-        dz2 *= 4.0 * (z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3]);
-        double sq[4];
-        oracle_quat_square(z, sq);
-        for (int k = 0; k < 4; ++k) z[k] = sq[k] + f->c[k];
-        m2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3];
+        dz2 *= julia_deriv_factor(z, deg);
+        double zp[4];
+        oracle_quat_pow(z, deg, zp);
+        for (int k = 0; k < 4; ++k) z[k] = zp[k] + f->c[k];
+        m2 = qlen2(z);
         if (m2 > f->bailout2) break;
         ++n;
     }
@@ -243,12 +289,13 @@ static double perturbed_de(const or_fractal* f, const double p[3], double rel, u
     if (f->kind == 0) {
         double z[4] = { p[0], p[1], p[2], 0.0 };
         double dz2 = 1.0, m2 = 0.0;
+        int32_t deg = julia_degree(f);
         for (int32_t i = 0; i < f->max_iter; ++i) {
-            dz2 *= 4.0 * (z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3]);
-            double sq[4];
-            oracle_quat_square(z, sq);
-            for (int k = 0; k < 4; ++k) z[k] = sq[k] * noise(seed, key, i, k, rel) + f->c[k];
-            m2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3];
+            dz2 *= julia_deriv_factor(z, deg);
+            double zp[4];
+            oracle_quat_pow(z, deg, zp);
+            for (int k = 0; k < 4; ++k) z[k] = zp[k] * noise(seed, key, i, k, rel) + f->c[k];
+            m2 = qlen2(z);
             if (m2 > f->bailout2) break;
         }
         return (m2 == 0.0) ? 0.0 : 0.25 * log(m2) * sqrt(m2 / dz2);
@@ -306,11 +353,12 @@ static double escape_margin(const or_fractal* f, const double p[3], int* escaped
     *escaped = 0;
     if (f->kind == 0) {
         double z[4] = { p[0], p[1], p[2], 0.0 };
+        int32_t deg = julia_degree(f);
         for (int32_t i = 0; i < f->max_iter; ++i) {
-            double sq[4];
-            oracle_quat_square(z, sq);
-            for (int k = 0; k < 4; ++k) z[k] = sq[k] + f->c[k];
-            double m2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2] + z[3] * z[3];
+            double zp[4];
+            oracle_quat_pow(z, deg, zp);
+            for (int k = 0; k < 4; ++k) z[k] = zp[k] + f->c[k];
+            double m2 = qlen2(z);
             best = fmin(best, fabs(m2 - f->bailout2) / f->bailout2);
             if (m2 > f->bailout2) { *escaped = 1; break; }
         }
@@ -340,13 +388,27 @@ void oracle_escape_margin(const or_fractal* f, const double* pts, int64_t n, dou
 }
 
 /* Bounding-sphere radius (R7): any point farther out escapes.
- * Julia: |z| > (1 + sqrt(1 + 4|c|))/2 implies |z^2 + c| >= |z|^2 - |c| > |z|.
+ * Julia of degree p: |z^p + c| >= |z|^p - |c| > |z| whenever |z| exceeds the
+ * root R >= 1 of R^p - R - |c| = 0; at p = 2 that root is
+ * (1 + sqrt(1 + 4|c|))/2, for larger p it is found by bisection on
+ * [1, 2 + |c|] (the polynomial is <= 0 at 1 and > 0 at 2 + |c|).
  * Mandelbulb: |p^n| = r^n, so the Multibrot bound 2^(1/(n-1)) applies.     */
 double oracle_bound_radius(const or_fractal* f) {
     double R;
     if (f->kind == 0) {
-        double cn = sqrt(f->c[0] * f->c[0] + f->c[1] * f->c[1] + f->c[2] * f->c[2] + f->c[3] * f->c[3]);
-        R = 0.5 * (1.0 + sqrt(1.0 + 4.0 * cn));
+        double cn = sqrt(qlen2(f->c));
+        int32_t deg = julia_degree(f);
+        if (deg == 2) {
+            R = 0.5 * (1.0 + sqrt(1.0 + 4.0 * cn));
+        } else {
+            double lo = 1.0, hi = 2.0 + cn;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                if (pow(mid, (double)deg) - mid - cn > 0.0) hi = mid; else lo = mid;
+            }
+            R = hi;
+        }
     } else {
         R = pow(2.0, 1.0 / (f->power - 1.0));
     }
@@ -702,23 +764,49 @@ static dual datan2(dual y, dual x) {
     return r;
 }
 
+/* Quaternion square, product and integer power (R1) in dual arithmetic.   */
+static void dquat_square(const dual z[4], dual out[4]) {
+    dual vv = dadd(dadd(dmul(z[1], z[1]), dmul(z[2], z[2])), dmul(z[3], z[3]));
+    dual a2 = dscale(z[0], 2.0);
+    out[0] = dsub(dmul(z[0], z[0]), vv);
+    out[1] = dmul(a2, z[1]);
+    out[2] = dmul(a2, z[2]);
+    out[3] = dmul(a2, z[3]);
+}
+static void dquat_mul(const dual x[4], const dual y[4], dual out[4]) {
+    dual r0 = dsub(dmul(x[0], y[0]), dadd(dadd(dmul(x[1], y[1]), dmul(x[2], y[2])), dmul(x[3], y[3])));
+    dual r1 = dadd(dadd(dmul(x[0], y[1]), dmul(y[0], x[1])), dsub(dmul(x[2], y[3]), dmul(x[3], y[2])));
+    dual r2 = dadd(dadd(dmul(x[0], y[2]), dmul(y[0], x[2])), dsub(dmul(x[3], y[1]), dmul(x[1], y[3])));
+    dual r3 = dadd(dadd(dmul(x[0], y[3]), dmul(y[0], x[3])), dsub(dmul(x[1], y[2]), dmul(x[2], y[1])));
+    out[0] = r0; out[1] = r1; out[2] = r2; out[3] = r3;
+}
+static void dquat_pow(const dual z[4], int32_t p, dual out[4]) {
+    dual w[4] = { z[0], z[1], z[2], z[3] };
+    if (p >= 2) dquat_square(z, w);
+    for (int32_t k = 3; k <= p; ++k) {
+        dual t[4];
+        dquat_mul(w, z, t);
+        for (int i = 0; i < 4; ++i) w[i] = t[i];
+    }
+    for (int i = 0; i < 4; ++i) out[i] = w[i];
+}
+static dual dqlen2(const dual z[4]) {
+    return dadd(dadd(dmul(z[0], z[0]), dmul(z[1], z[1])), dadd(dmul(z[2], z[2]), dmul(z[3], z[3])));
+}
+
 /* Julia distance in dual arithmetic, same steps as julia_de. */
 static dual julia_de_dual(const or_fractal* f, const dual c[4], const dual p[3], int32_t* iters) {
     dual z[4] = { p[0], p[1], p[2], dc(0.0) };
     dual dz2 = dc(1.0), m2 = dc(0.0);
     int32_t n = 0;
+    int32_t deg = julia_degree(f);
     for (int32_t i = 0; i < f->max_iter; ++i) {
-        dual zz = dadd(dadd(dmul(z[0], z[0]), dmul(z[1], z[1])), dadd(dmul(z[2], z[2]), dmul(z[3], z[3])));
-        dz2 = dmul(dz2, dscale(zz, 4.0));
-        dual vv = dadd(dadd(dmul(z[1], z[1]), dmul(z[2], z[2])), dmul(z[3], z[3]));
-        dual a2 = dscale(z[0], 2.0);
-        dual nz[4];
-        nz[0] = dadd(dsub(dmul(z[0], z[0]), vv), c[0]);
-        nz[1] = dadd(dmul(a2, z[1]), c[1]);
-        nz[2] = dadd(dmul(a2, z[2]), c[2]);
-        nz[3] = dadd(dmul(a2, z[3]), c[3]);
-        for (int k = 0; k < 4; ++k) z[k] = nz[k];
-        m2 = dadd(dadd(dmul(z[0], z[0]), dmul(z[1], z[1])), dadd(dmul(z[2], z[2]), dmul(z[3], z[3])));
+        dual zq[4], zp[4];
+        dquat_pow(z, deg - 1, zq);
+        dz2 = dmul(dz2, dscale(dqlen2(zq), (double)deg * (double)deg));
+        dquat_pow(z, deg, zp);
+        for (int k = 0; k < 4; ++k) z[k] = dadd(zp[k], c[k]);
+        m2 = dqlen2(z);
         if (m2.v > f->bailout2) break;
         ++n;
     }

@@ -69,6 +69,8 @@ def lib():
         P = ctypes.POINTER
         dp = P(ctypes.c_double)
         L.oracle_quat_square.argtypes = [dp, dp]
+        L.oracle_quat_mul.argtypes = [dp, dp, dp]
+        L.oracle_quat_pow.argtypes = [dp, ctypes.c_int32, dp]
         L.oracle_bulb_power.argtypes = [dp, ctypes.c_double, dp]
         L.oracle_escape_iters.argtypes = [P(Fractal), dp, ctypes.c_int32]
         L.oracle_escape_iters.restype = ctypes.c_int32
@@ -108,7 +110,10 @@ def make_camera(cam):
 def make_fractal(fr):
     kind = {"julia": 0, "bulb": 1}[fr["kind"]]
     c = list(fr.get("c", (0.0, 0.0, 0.0, 0.0)))
-    return Fractal(kind, c_double4(*c), float(fr.get("power", 8.0)), int(fr["max_iter"]), float(fr["bailout2"]),
+    power = float(fr.get("power", 2.0 if kind == 0 else 8.0))
+    if kind == 0 and (power != int(power) or not 2 <= power <= 16):
+        raise ValueError("Julia degree must be an integer in [2, 16], got %r" % power)
+    return Fractal(kind, c_double4(*c), power, int(fr["max_iter"]), float(fr["bailout2"]),
                    float(fr.get("bound_radius", 0.0)))
 
 
@@ -213,6 +218,21 @@ def quat_square(z):
     z = np.ascontiguousarray(z, dtype=np.float64)
     out = np.empty(4)
     lib().oracle_quat_square(_ptr(z, ctypes.c_double), _ptr(out, ctypes.c_double))
+    return out
+
+
+def quat_mul(x, y):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.empty(4)
+    lib().oracle_quat_mul(_ptr(x, ctypes.c_double), _ptr(y, ctypes.c_double), _ptr(out, ctypes.c_double))
+    return out
+
+
+def quat_pow(z, p):
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    out = np.empty(4)
+    lib().oracle_quat_pow(_ptr(z, ctypes.c_double), int(p), _ptr(out, ctypes.c_double))
     return out
 
 

@@ -21,6 +21,9 @@ CASES = {
     "julia_two_planes": (lambda: W.julia_view(width=40, height=40, planes=[W.plane([0.6, 0.0, 0.8], 0.0),
                                                                            W.plane([-0.6, 0.0, 0.8], 0.0)]),
                          [0, 3, 5, 8, 9, 10, 11, 12]),
+    "julia_cubic_cut": (lambda: W.julia_view(width=44, height=44, degree=3, c=[-0.45, 0.1, 0.4, 0.2],
+                                             planes=[W.plane([-0.2, 0.3, 1.0], 0.1)]),
+                        [0, 1, 2, 3, 5, 6, 7, 8]),
     "bulb_cut_shadow": (lambda: W.bulb_view(0.7, 0.2, width=40, height=40, shadow=True,
                                             planes=[W.plane([0.2, 1.0, 0.1], 0.1)]), [4, 5, 6, 7, 8]),
     "bulb_real_power": (lambda: W.bulb_view(2.1, -0.3, width=40, height=40, power=6.37, shadow=False),

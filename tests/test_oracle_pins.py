@@ -36,6 +36,32 @@ def test_quat_square_matches_matrix_representation(orc):
         assert abs(np.dot(got, got) - np.dot(q, q) ** 2) <= 1e-12 * np.dot(q, q) ** 2
 
 
+def test_quat_product_matches_matrix_representation(orc):
+    """General (non-commuting) products: the cross term of the Hamilton
+    product is what a transposed operand or a sign slip would break."""
+    rng = np.random.default_rng(12)
+    for _ in range(200):
+        x, y = rng.normal(size=4), rng.normal(size=4)
+        m = _qmat(x) @ _qmat(y)
+        ref = np.array([m[0, 0].real, m[0, 0].imag, m[0, 1].real, m[0, 1].imag])
+        np.testing.assert_allclose(orc.quat_mul(x, y), ref, rtol=1e-13, atol=1e-13)
+    x, y = np.array([0.0, 1.0, 0.0, 0.0]), np.array([0.0, 0.0, 1.0, 0.0])
+    np.testing.assert_array_equal(orc.quat_mul(x, y), [0.0, 0.0, 0.0, 1.0])       # i j = k
+    np.testing.assert_array_equal(orc.quat_mul(y, x), [0.0, 0.0, 0.0, -1.0])      # j i = -k
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 8, 13])
+def test_quat_power_matches_matrix_power(orc, p):
+    rng = np.random.default_rng(13 + p)
+    for _ in range(100):
+        q = rng.normal(size=4) * 0.6
+        m = np.linalg.matrix_power(_qmat(q), p)
+        ref = np.array([m[0, 0].real, m[0, 0].imag, m[0, 1].real, m[0, 1].imag])
+        got = orc.quat_pow(q, p)
+        tol = 1e-13 * max(1.0, np.dot(q, q) ** (p / 2))
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=tol)
+
+
 # ------------------------------------------------------------- Julia estimate
 @pytest.mark.parametrize("max_iter,rmin", [(1, 0.3), (3, 0.3), (11, 0.95)])
 def test_julia_c0_estimate_is_half_r_log_r(orc, max_iter, rmin):
@@ -49,31 +75,66 @@ def test_julia_c0_estimate_is_half_r_log_r(orc, max_iter, rmin):
     np.testing.assert_allclose(d, ref, rtol=1e-12, atol=1e-15)
 
 
-def _complex_orbit(z0, c, max_iter, bailout2):
-    """Orbit of z -> z^2 + c from z0, stopping as the estimator does."""
+@pytest.mark.parametrize("degree,max_iter,rmin", [(3, 3, 0.3), (3, 6, 0.9), (5, 3, 0.5), (7, 2, 0.3),
+                                                  (16, 2, 0.7)])
+def test_julia_degree_c0_estimate_is_half_r_log_r(orc, degree, max_iter, rmin):
+    """c = 0, degree p: |z_k| = r^(p^k) and |z_k'| = p^k r^(p^k - 1), so
+    0.5 |z| ln|z| / |z'| = 0.5 r ln r whatever p and k; the orbit escapes
+    at the first k with r^(2 p^k) > bailout2."""
+    rng = np.random.default_rng(40 + degree + max_iter)
+    dirs = rng.normal(size=(500, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    r = rng.uniform(rmin, 3.0, size=500)
+    pts = dirs * r[:, None]
+    d, it, _, _ = orc.de(W.julia([0, 0, 0, 0], max_iter, degree=degree), pts)
+    ref = GOLDEN["julia_c0"]["de_factor"] * r * np.log(r)
+    np.testing.assert_allclose(d, ref, rtol=1e-12, atol=1e-15)
+    ref_it = np.full(r.size, max_iter)
+    for i, ri in enumerate(r):
+        for k in range(1, max_iter + 1):
+            if 2.0 * degree ** k * math.log(ri) > math.log(256.0):
+                ref_it[i] = k - 1
+                break
+    np.testing.assert_array_equal(it, ref_it)
+
+
+def _complex_orbit(z0, c, max_iter, bailout2, degree=2):
+    """Orbit of z -> z^p + c from z0, stopping as the estimator does."""
     z, n, bodies = z0, 0, 0
     for _ in range(max_iter):
         bodies += 1
-        z = z * z + c
+        z = z ** degree + c
         if abs(z) ** 2 > bailout2:
             break
         n += 1
     return z, n, bodies
 
 
-def _complex_iter_fixed(z0, c, bodies):
+def _complex_iter_fixed(z0, c, bodies, degree=2):
     z = z0
     for _ in range(bodies):
-        z = z * z + c
+        z = z ** degree + c
     return z
 
 
-@pytest.mark.parametrize("axis", ["ij", "k"])
-def test_julia_complex_slice_matches_complex_dynamics(orc, axis):
-    """In span{1, u} the quaternion map is the complex map z^2+c' (a complex
+def _holomorphic_derivative(fn, z0, rho=1e-5, n=16):
+    """f'(z0) by Cauchy's integral formula on the circle |z - z0| = rho,
+    trapezoid rule with n nodes: exact up to the aliased Taylor terms
+    a_(1+jn) rho^(jn) and a rounding error ~ 1e-16 max|f| / rho.
+    Returns the derivative and a bound on that rounding error."""
+    w = np.exp(2j * np.pi * np.arange(n) / n)
+    vals = [fn(z0 + rho * wk) for wk in w]
+    der = sum(v / wk for v, wk in zip(vals, w)) / (n * rho)
+    return der, 64 * np.finfo(float).eps * max(abs(v) for v in vals) / rho
+
+
+@pytest.mark.parametrize("axis,degree", [("ij", 2), ("k", 2), ("ij", 3), ("k", 3), ("ij", 4), ("ij", 6)])
+def test_julia_complex_slice_matches_complex_dynamics(orc, axis, degree):
+    """In span{1, u} the quaternion map is the complex map z^p+c' (a complex
     subalgebra), so orbit, escape count and running derivative must equal
-    the complex ones; the derivative is checked by finite differences."""
-    rng = np.random.default_rng(21 if axis == "ij" else 22)
+    the complex ones; the derivative is checked against a contour-integral
+    derivative of the complex orbit map."""
+    rng = np.random.default_rng((21 if axis == "ij" else 22) + 100 * degree)
     if axis == "k":
         u = np.array([0.0, 0.0, 0.0, 1.0])      # the k axis: slice points must be real
     else:
@@ -82,22 +143,23 @@ def test_julia_complex_slice_matches_complex_dynamics(orc, axis):
         u = np.array([0.0, v[0], v[1], 0.0])
     c0, s = -0.3, 0.55
     c = np.array([c0, 0, 0, 0]) + s * u
-    fr = W.julia(c, 11)
+    max_iter = {2: 11, 3: 8, 4: 6, 6: 5}[degree]
+    fr = W.julia(c, max_iter, degree=degree)
     fr["c"] = list(c)                      # keep doubles for this pin
     for _ in range(60):
         x = rng.uniform(-1.5, 1.5)
         y = 0.0 if axis == "k" else rng.uniform(-1.5, 1.5)
         p = np.array([x, y * u[1], y * u[2]])
         d, it, m2, dz2 = (a[0] for a in orc.de(fr, p[None, :]))
-        zN, n, bodies = _complex_orbit(complex(x, y), complex(c0, s), 11, 256.0)
+        zN, n, bodies = _complex_orbit(complex(x, y), complex(c0, s), max_iter, 256.0, degree)
         assert it == n
         assert m2 == pytest.approx(abs(zN) ** 2, rel=1e-11)
-        h = 1e-6
-        dzN = (_complex_iter_fixed(complex(x + h, y), complex(c0, s), bodies)
-               - _complex_iter_fixed(complex(x - h, y), complex(c0, s), bodies)) / (2 * h)
-        assert math.sqrt(dz2) == pytest.approx(abs(dzN), rel=1e-5)
+        dzN, err = _holomorphic_derivative(lambda z: _complex_iter_fixed(z, complex(c0, s), bodies, degree),
+                                           complex(x, y))
+        rel = 1e-9 + err / abs(dzN)
+        assert abs(math.sqrt(dz2) - abs(dzN)) <= rel * abs(dzN)
         ref_d = 0.5 * abs(zN) * math.log(abs(zN)) / abs(dzN)
-        assert d == pytest.approx(ref_d, rel=1e-5, abs=1e-12)
+        assert abs(d - ref_d) <= 2 * rel * abs(ref_d) + 1e-15
 
 
 def test_julia_estimate_is_even(orc):
@@ -226,12 +288,27 @@ def test_bound_radius_values(orc):
     assert R * R - R - cn == pytest.approx(0.0, abs=1e-14)
 
 
+@pytest.mark.parametrize("degree", [3, 4, 5, 7])
+def test_julia_degree_bound_radius_is_the_tight_escape_radius(orc, degree):
+    """R solves R^p - R - |c| = 0; for c = -|c| on the real axis the point
+    (R, 0, 0) is a fixed point of x^p - |c| (x^p - |c| = x), so just inside R
+    the orbit stays put for a few bodies while just outside it escapes."""
+    for cn in (0.0, 0.2, 0.7, 1.3):
+        fr = W.julia([-cn, 0, 0, 0], 6, degree=degree)
+        fr["c"] = [-cn, 0.0, 0.0, 0.0]
+        R = orc.bound_radius(fr)
+        assert R >= 1.0
+        assert abs(R ** degree - R - cn) <= 1e-13 * R ** degree
+        assert orc.escape_iters(fr, np.array([[R * (1.0 - 1e-13), 0.0, 0.0]]), 6)[0] == 6
+        assert orc.escape_iters(fr, np.array([[R * (1.0 + 1e-9), 0.0, 0.0]]), 10000)[0] < 10000
+
+
 @pytest.mark.parametrize("kind", ["julia", "bulb"])
 def test_points_beyond_bound_radius_escape(orc, kind):
     rng = np.random.default_rng(80)
     for trial in range(20):
         if kind == "julia":
-            fr = W.julia(rng.uniform(-0.8, 0.8, size=4), 10000)
+            fr = W.julia(rng.uniform(-0.8, 0.8, size=4), 10000, degree=int(rng.integers(2, 8)))
         else:
             fr = W.bulb(rng.uniform(2.0, 16.0), 10000)
         R = orc.bound_radius(fr)

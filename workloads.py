@@ -52,9 +52,10 @@ def march(max_steps, eps_abs=0.0, eps_rel=0.0, normal_mode="tetra", shadow=False
             "albedo": list(ALBEDO), "k_ambient": K_AMBIENT, "k_diffuse": K_DIFFUSE}
 
 
-def julia(c, max_iter, bailout2=256.0, bound_radius=0.0):
-    return {"kind": "julia", "c": f32v(c), "power": 2.0, "max_iter": int(max_iter), "bailout2": f32(bailout2),
-            "bound_radius": f32(bound_radius)}
+def julia(c, max_iter, bailout2=256.0, bound_radius=0.0, degree=2):
+    """Quaternion Julia z^p + c; `degree` is the integer p (stored as power)."""
+    return {"kind": "julia", "c": f32v(c), "power": float(int(degree)), "max_iter": int(max_iter),
+            "bailout2": f32(bailout2), "bound_radius": f32(bound_radius)}
 
 
 def bulb(power, max_iter, bailout2=4.0, bound_radius=0.0):
@@ -76,8 +77,8 @@ def job(cam, frac, mc, planes=()):
 # normals, Lambert shading.
 # ---------------------------------------------------------------------------
 def julia_view(c=JULIA_C1, width=256, height=256, max_iter=11, max_steps=256, eps_abs=1e-3, planes=(),
-               eye=(0.0, 0.0, 3.0), shadow=False, normal_mode="tetra"):
-    return job(camera(eye, width, height), julia(c, max_iter),
+               eye=(0.0, 0.0, 3.0), shadow=False, normal_mode="tetra", degree=2):
+    return job(camera(eye, width, height), julia(c, max_iter, degree=degree),
                march(max_steps, eps_abs=eps_abs, normal_mode=normal_mode, shadow=shadow), planes)
 
 
