@@ -4,7 +4,8 @@
  * Renders escape-time fractals by per-pixel sphere tracing, after da Silva,
  * Novello, Lopes and Velho, "Real-time rendering of complex fractals"
  * (arXiv 2102.01747):
- *   - the quaternion Julia set z^2 + c (Sec. 1.1), sliced to 3-D with the
+ *   - the quaternion Julia set z^p + c (Sec. 1.1 at p = 2, Eq. 3-4 and the
+ *     cubic of Listing 4 for higher integer degrees), sliced to 3-D with the
  *     fourth quaternion component zero and optionally cut by planes (Fig. 1
  *     and the text around Listing 3);
  *   - the White-Nylander power-n Mandelbulb (Sec. 1.2, Eq. 1, Listing 7).
@@ -79,16 +80,20 @@ typedef struct {
 } frt_camera;
 
 /* Fractal (Sec. 1.1, 1.2).  Julia: z0 = (x, y, z, 0) with component 0 the
- * real part, z <- z^2 + c (Eq. 3).  Mandelbulb: w0 = p, w <- w^n + p with the
+ * real part, z <- z^p + c (Eq. 3) for an integer degree p in [2, 16] given
+ * in `power` (Listing 4 is p = 3), with the squared derivative gaining
+ * p^2 |z|^(2(p-1)) per body (Eq. 4 in norm); bailout2^p must be below 2^120
+ * so that the escaping body's |z|^2 stays finite in float32.  Mandelbulb: w0 = p, w <- w^n + p with the
  * power map of Eq. 1 in Listing 7's axes (y polar, azimuth atan2(x, z)),
  * any real n >= 2.  An orbit stops after max_iter bodies or when |z|^2
  * exceeds bailout2.  The march is confined to a sphere whose radius is the
- * larger of the provable escape radius ((1 + sqrt(1 + 4|c|))/2 for Julia,
+ * larger of the provable escape radius (the root R >= 1 of R^p - R - |c|
+ * for Julia, (1 + sqrt(1 + 4|c|))/2 at p = 2,
  * 2^(1/(n-1)) for the Mandelbulb) and bound_radius (0 for automatic).      */
 typedef struct {
     int32_t kind;               /* FRT_JULIA or FRT_MANDELBULB               */
     float c[4];                 /* Julia constant; ignored for Mandelbulb    */
-    float power;                /* Mandelbulb n >= 2; ignored for Julia      */
+    float power;                /* Mandelbulb n >= 2; Julia degree p         */
     int32_t max_iter;           /* [1, 4096]                                 */
     float bailout2;             /* > 0                                       */
     float bound_radius;         /* >= 0                                      */
@@ -163,7 +168,8 @@ frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_
                       void* workspace, size_t ws_bytes, void* stream);
 
 /* Render n_jobs independent views in one persistent launch per kernel
- * variant present (Julia, Mandelbulb with real, integer or n = 8 power): the
+ * variant present (Julia of degree 2 or of higher degree, Mandelbulb with
+ * real, integer or n = 8 power): the
  * rays of a variant's jobs form one index space that its waves drain through
  * a shared queue.
  * jobs: host array of n_jobs (>= 1) entries; workspace: device memory of
@@ -189,7 +195,8 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
  * The result is, per job, the gradient of
  *   sum_p g_colour . colour + g_depth depth + g_normal . normal
  * with respect to theta = (c0..c3 | power | plane 0 raw n xyz, d |
- * plane 1 raw n xyz, d); slots a job does not use come out zero.
+ * plane 1 raw n xyz, d); slots a job does not use come out zero (power for
+ * Julia jobs, whose degree is discrete; c for the Mandelbulb).
  * jobs: the forward jobs, with out.depth and out.status holding the forward
  *       results (the other out pointers are not read);
  * g_colour / g_depth / g_normal: host arrays of n_jobs device pointers to
@@ -224,8 +231,9 @@ frt_status frt_distance(const frt_fractal* frac, const float* points, int64_t n,
 frt_status frt_math_eval(int32_t func, const float* x, const float* y, float* out, int64_t n, void* stream);
 
 /* Launch configuration of the persistent kernels, chosen by the autotuner.
- * kernel_variant: 0 Julia, 1 Mandelbulb (real n), 2 Mandelbulb (integer n),
- * 3 Mandelbulb with n = 8 (the power the paper renders).  A batch is traced
+ * kernel_variant: 0 Julia z^2 + c, 1 Mandelbulb (real n), 2 Mandelbulb
+ * (integer n), 3 Mandelbulb with n = 8 (the power the paper renders),
+ * 4 Julia z^p + c with p >= 3.  A batch is traced
  * as one group of rays per variant present, each with its own setting.
  * block: 64, 128, 256 or 512 threads; chunk: rays taken from the queue per
  * refill, a multiple of 64 in [64, 4096]; waves_per_simd: resident waves per

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libfrt.so")
 FRT_OK, FRT_EINVAL, FRT_EHIP, FRT_ENOMEM, FRT_EUNSUPPORTED = 0, -1, -2, -3, -4
 STATUS_MISS_BOUNDS, STATUS_MISS_TMAX, STATUS_HIT, STATUS_HIT_CUT, STATUS_HIT_EXHAUSTED = 0, 1, 2, 3, 4
 FLAG_SHADOWED, FLAG_UNREFINED, FLAG_SHADOW_RAY = 8, 16, 64
-VARIANTS = {"julia": 0, "bulb_real": 1, "bulb_int": 2, "bulb8": 3}
+VARIANTS = {"julia": 0, "bulb_real": 1, "bulb_int": 2, "bulb8": 3, "julia_deg": 4}
 
 f3 = ctypes.c_float * 3
 f4 = ctypes.c_float * 4

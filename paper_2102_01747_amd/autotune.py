@@ -34,7 +34,7 @@ def variants_of(jobs):
     for j in jobs:
         fr = j["fractal"]
         if fr["kind"] == "julia":
-            v = "julia"
+            v = "julia" if float(fr.get("power", 2.0)) == 2.0 else "julia_deg"
         else:
             n = float(fr["power"])
             v = "bulb8" if n == 8.0 else ("bulb_int" if n.is_integer() and 2 <= n <= 64 else "bulb_real")
@@ -135,8 +135,9 @@ def main():
     """Tune the launch configuration on one of the reference workloads and
     record it in tuned.json: python -m paper_2102_01747_amd.autotune WORKLOAD
     with WORKLOAD one of bulb_views (8 x 1080p Mandelbulb, n = 8),
-    julia_batch (64 uneven Julia renders), diff_set (16 x 512^2, Julia and
-    Mandelbulb), stress (the 4K power sweep: real and integer powers)."""
+    julia_batch (64 uneven Julia renders), julia_degree_batch (32 Julia
+    renders of degree 3-6), diff_set (16 x 512^2, Julia and Mandelbulb),
+    stress (the 4K power sweep: real and integer powers)."""
     import argparse
     import sys
 
@@ -144,14 +145,14 @@ def main():
     import workloads as W
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("workload", choices=["bulb_views", "julia_batch", "diff_set", "stress"])
+    ap.add_argument("workload", choices=["bulb_views", "julia_batch", "julia_degree_batch", "diff_set", "stress"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--out", default=TUNED_PATH)
     ap.add_argument("--variants", nargs="*", default=None,
                     help="tune only these kernel variants (default: every variant the workload uses)")
     args = ap.parse_args()
-    jobs = {"bulb_views": W.bulb_views, "julia_batch": W.julia_batch,
+    jobs = {"bulb_views": W.bulb_views, "julia_batch": W.julia_batch, "julia_degree_batch": W.julia_degree_batch,
             "diff_set": lambda: W.diff_set()[0], "stress": W.stress_sweep}[args.workload]()
     for res in tune(jobs, batch=True, reps=args.reps, passes=args.passes, log=lambda m: print(m, flush=True),
                     variants=args.variants):

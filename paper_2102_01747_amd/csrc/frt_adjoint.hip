@@ -46,11 +46,14 @@ namespace frt {
 // forward pass.  The transcendentals are the device library's FP64 ones.
 
 // ---------------------------------------------------------------------------
-// Julia z^2 + c (same loop as JuliaOrbit) with NP + 1 tangents: slots
-// 0..NP-1 the constant c (z'_0 = 0, +e_s every body; NP = 4 or 0), slot NP
-// the spatial direction v (z'_0 = (v, 0)).  The running derivative product
+// Julia z^p + c (same loop as JuliaOrbit / JuliaDegOrbit) with NP + 1
+// tangents: slots 0..NP-1 the constant c (z'_0 = 0, +e_s every body; NP = 4
+// or 0), slot NP the spatial direction v (z'_0 = (v, 0)).  z^p comes from
+// the recurrence on z^j = R_j + Q_j v (R_1 = a, Q_1 = 1,
+// R_(j+1) = a R_j - |v|^2 Q_j, Q_(j+1) = R_j + a Q_j), differentiated term
+// by term.  The running derivative product (p^2 |z|^(2(p-1)) per body)
 // enters only through its logarithm, so its tangent is carried as
-// L = d ln(dz2) = sum 2 z.z'/|z|^2.  d = A S with A = 0.25 ln m2,
+// L = d ln(dz2) = sum 2 (p-1) z.z'/|z|^2.  d = A S with A = 0.25 ln m2,
 // S = sqrt(m2 / dz2):
 //   d' = S (m2'/m2) (0.25 + 0.5 A) - 0.5 A S L.
 // ---------------------------------------------------------------------------
@@ -60,6 +63,9 @@ __device__ __forceinline__ void julia_de_tan(const OrbitParams& P, double x, dou
                                              double& dv) {
     constexpr int K = NP + 1;
     const double c0 = P.c0, c1 = P.c1, c2 = P.c2, c3 = P.c3;
+    const int deg = P.ipow;
+    const double lfac = 2.0 * (deg - 1);
+    const double p2 = static_cast<double>(deg) * deg;
     double a = x, b = y, e = z, w = 0.0;
     double ta[K], tb[K], te[K], tw[K], L[K];
 #pragma unroll
@@ -70,28 +76,44 @@ __device__ __forceinline__ void julia_de_tan(const OrbitParams& P, double x, dou
     int bodies = 0;
     for (int i = 0; i < P.max_iter; ++i) {
         const double im2 = m2 > 0.0 ? 1.0 / m2 : 0.0;
-        prod *= m2;
-        const double a2 = a + a;
+        const double vv = fma(b, b, fma(e, e, w * w));
+        // primal z^p = R + Q v and |z|^(2(p-1))
+        double R = a, Q = 1.0, mp = 1.0;
+        for (int j = 1; j < deg; ++j) {
+            const double nR = fma(a, R, -vv * Q);
+            Q = fma(a, Q, R);
+            R = nR;
+            mp *= m2;
+        }
+        prod *= mp * p2;
+        // tangents one slot at a time (the primal recurrence is rerun per
+        // slot rather than holding every slot's (R', Q') at once)
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             const double dot = fma(a, ta[s], fma(b, tb[s], fma(e, te[s], w * tw[s])));
-            L[s] = fma(2.0 * dot, im2, L[s]);
-            const double na = 2.0 * (a * ta[s] - fma(b, tb[s], fma(e, te[s], w * tw[s])));
-            const double t2 = ta[s] + ta[s];
-            const double nb = fma(t2, b, a2 * tb[s]);
-            const double ne = fma(t2, e, a2 * te[s]);
-            const double nw = fma(t2, w, a2 * tw[s]);
-            ta[s] = na + ((s < NP && s == 0) ? 1.0 : 0.0);
+            L[s] = fma(lfac * dot, im2, L[s]);
+            const double dvv = 2.0 * fma(b, tb[s], fma(e, te[s], w * tw[s]));
+            double r = a, q = 1.0, dr = ta[s], dq = 0.0;
+            for (int j = 1; j < deg; ++j) {
+                const double ndr = fma(ta[s], r, fma(a, dr, -fma(dvv, q, vv * dq)));
+                dq = fma(ta[s], q, fma(a, dq, dr));
+                dr = ndr;
+                const double nr = fma(a, r, -vv * q);
+                q = fma(a, q, r);
+                r = nr;
+            }
+            const double nb = fma(dq, b, Q * tb[s]);
+            const double ne = fma(dq, e, Q * te[s]);
+            const double nw = fma(dq, w, Q * tw[s]);
+            ta[s] = dr + ((s < NP && s == 0) ? 1.0 : 0.0);
             tb[s] = nb + ((s < NP && s == 1) ? 1.0 : 0.0);
             te[s] = ne + ((s < NP && s == 2) ? 1.0 : 0.0);
             tw[s] = nw + ((s < NP && s == 3) ? 1.0 : 0.0);
         }
-        const double vv = fma(b, b, fma(e, e, w * w));
-        const double na = fma(a, a, -vv) + c0;
-        b = fma(a2, b, c1);
-        e = fma(a2, e, c2);
-        w = fma(a2, w, c3);
-        a = na;
+        a = R + c0;
+        b = fma(Q, b, c1);
+        e = fma(Q, e, c2);
+        w = fma(Q, w, c3);
         m2 = fma(a, a, fma(b, b, fma(e, e, w * w)));
         ++bodies;
         if (m2 > P.bail2) break;
@@ -103,7 +125,7 @@ __device__ __forceinline__ void julia_de_tan(const OrbitParams& P, double x, dou
         dv = 0.0;
         return;
     }
-    const double dz2 = ldexp(prod, 2 * bodies);
+    const double dz2 = prod;
     const double S = sqrt(m2 / dz2);
     const double A = 0.25 * log(m2);
     d = A * S;

@@ -65,6 +65,7 @@ Tune g_tune[frt::kNumVariants] = {
     {64, 256, 0, 8, 16},   // Mandelbulb, real power
     {64, 256, 0, 8, 16},   // Mandelbulb, integer power
     {64, 256, 0, 8, 16},   // Mandelbulb, n = 8
+    {64, 256, 0, 8, 16},   // Julia, degree >= 3
 };
 
 int device_cus() {
@@ -171,6 +172,15 @@ bool validate(const frt_camera* cam, const frt_fractal* fr, const frt_plane* pla
     if (!(fr->bailout2 > 0.0f)) { why = "bailout2 must be > 0"; return false; }
     if (!(fr->bound_radius >= 0.0f)) { why = "bound_radius must be >= 0"; return false; }
     if (fr->kind == FRT_MANDELBULB && !(fr->power >= 2.0f)) { why = "Mandelbulb power must be >= 2"; return false; }
+    if (fr->kind == FRT_JULIA) {
+        if (!(fr->power >= 2.0f && fr->power <= 16.0f && std::floor(fr->power) == fr->power)) {
+            why = "Julia degree (power) must be an integer in [2, 16]"; return false;
+        }
+        // the escaping body's |z|^2 is at most about bailout2^p: keep it finite in float
+        if (!(double(fr->power) * std::log2(double(fr->bailout2)) <= 120.0)) {
+            why = "Julia bailout2^degree must be below 2^120"; return false;
+        }
+    }
     if (n_planes < 0 || n_planes > 2) { why = "n_planes must be in [0, 2]"; return false; }
     if (n_planes > 0 && !planes) { why = "planes is null"; return false; }
     for (int k = 0; k < n_planes; ++k) {
@@ -244,11 +254,25 @@ void pack(const frt_camera* cam, const frt_fractal* fr, const frt_plane* planes,
     for (int k = 0; k < 4; ++k) J.c[k] = fr->kind == FRT_JULIA ? fr->c[k] : 0.0f;
     double R;
     if (fr->kind == FRT_JULIA) {
-        J.power = 2.0f;
+        // degree p: the escape radius is the root R >= 1 of R^p - R - |c|
+        const int p = int(fr->power);
+        J.power = float(p);
+        J.int_power = p;
         const double cn = std::sqrt(double(fr->c[0]) * fr->c[0] + double(fr->c[1]) * fr->c[1] +
                                     double(fr->c[2]) * fr->c[2] + double(fr->c[3]) * fr->c[3]);
-        R = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * cn));
-        J.int_power = 2;
+        if (p == 2) {
+            R = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * cn));
+        } else {
+            // Newton from the right of the root: the polynomial is convex and
+            // increasing there, so the iterates decrease monotonically onto it
+            R = 2.0 + cn;
+            for (int it = 0; it < 100; ++it) {
+                const double rp1 = std::pow(R, p - 1);
+                const double step = (rp1 * R - R - cn) / (p * rp1 - 1.0);
+                if (!(step > 0.0)) break;
+                R -= step;
+            }
+        }
     } else {
         J.power = fr->power;
         R = std::pow(2.0, 1.0 / (double(fr->power) - 1.0));
@@ -293,7 +317,7 @@ void pack(const frt_camera* cam, const frt_fractal* fr, const frt_plane* planes,
 }
 
 int variant_of(const JobDev& J) {
-    if (J.kind == FRT_JULIA) return frt::kVarJulia;
+    if (J.kind == FRT_JULIA) return J.int_power == 2 ? frt::kVarJulia : frt::kVarJuliaDeg;
     if (J.int_power == 8) return frt::kVarBulb8;
     return J.int_power > 0 ? frt::kVarBulbInt : frt::kVarBulbReal;
 }

@@ -105,6 +105,76 @@ struct JuliaOrbit {
 };
 
 // ---------------------------------------------------------------------------
+// Quaternion Julia z^p + c for an integer degree p >= 2 read at run time
+// (Eq. 3-4; Listing 4 is the cubic).  Powers of one quaternion z = a + v stay
+// in the plane span{1, v}: z^j = R_j + Q_j v with R_1 = a, Q_1 = 1 and, since
+// v v = -|v|^2,
+//   R_(j+1) = a R_j - |v|^2 Q_j,   Q_(j+1) = R_j + a Q_j,
+// three operations per degree and no square root (z^2 = a^2 - |v|^2 + 2a v
+// is the first step).  The squared running derivative gains
+// p^2 |z|^(2(p-1)) per body (Eq. 4 taken in norm; the quaternion norm is
+// multiplicative).
+// ---------------------------------------------------------------------------
+struct JuliaDegOrbit {
+    float a, b, e, w, m2, dz2;
+    int k;
+
+    __device__ __forceinline__ void init(float x, float y, float z) {
+        a = x; b = y; e = z; w = 0.0f;
+        m2 = fmaf(a, a, fmaf(b, b, e * e));
+        dz2 = 1.0f;
+        k = 0;
+    }
+    // z^p + c into (na, nb, ne, nw) and the body's derivative factor
+    __device__ __forceinline__ void map(const OrbitParams& P, float& na, float& nb, float& ne, float& nw,
+                                        float& fac) const {
+        const float vv = fmaf(b, b, fmaf(e, e, w * w));
+        float R = fmaf(a, a, -vv), Q = a + a, mp = m2;
+        for (int j = 2; j < P.ipow; ++j) {
+            const float nR = fmaf(a, R, -vv * Q);
+            Q = fmaf(a, Q, R);
+            R = nR;
+            mp *= m2;
+        }
+        na = R + P.c0;
+        nb = fmaf(Q, b, P.c1);
+        ne = fmaf(Q, e, P.c2);
+        nw = fmaf(Q, w, P.c3);
+        fac = (P.n * P.n) * mp;
+    }
+    __device__ __forceinline__ bool body(const OrbitParams& P) {
+        float na, nb, ne, nw, fac;
+        map(P, na, nb, ne, nw, fac);
+        a = na; b = nb; e = ne; w = nw;
+        dz2 *= fac;
+        m2 = fmaf(a, a, fmaf(b, b, fmaf(e, e, w * w)));
+        ++k;
+        return !(m2 > P.bail2);
+    }
+    __device__ __forceinline__ unsigned long long step(const OrbitParams& P, unsigned long long live_mask) {
+        const bool live = __builtin_amdgcn_inverse_ballot_w64(live_mask);
+        float na, nb, ne, nw, fac;
+        map(P, na, nb, ne, nw, fac);
+        a = na; b = nb; e = ne; w = nw;
+        const float dn = dz2 * fac;
+        const float mn = fmaf(a, a, fmaf(b, b, fmaf(e, e, w * w)));
+        const int kn = k + 1;
+        dz2 = live ? dn : dz2;
+        m2 = live ? mn : m2;
+        k = live ? kn : k;
+        return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2) && kn < P.max_iter);
+    }
+    __device__ __forceinline__ DEResult result(const OrbitParams& P) const {
+        DEResult r;
+        const bool esc = m2 > P.bail2;
+        r.bodies = k;
+        r.it = esc ? k - 1 : k;
+        r.d = m2 > 0.0f ? kQuarterLn2 * hw_log2(m2) * (m2 * hw_rsq(m2)) * hw_rsq(dz2) : 0.0f;
+        return r;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // White-Nylander Mandelbulb (Listing 7 generalised to any n >= 2): y is the
 // polar axis, theta = acos(y/r), phi = atan2(x, z);
 //   dr <- n r^(n-1) dr + 1,  w <- r^n (sin n th sin n ph, cos n th, sin n th cos n ph) + p.

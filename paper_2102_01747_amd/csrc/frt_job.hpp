@@ -12,11 +12,12 @@ enum Kind : int32_t { kJulia = 0, kBulb = 1 };
 // kernel variants (template argument and autotuner key); a batch is split
 // into one group of rays per variant present, each traced by its own kernels
 enum Variant : int32_t {
-    kVarJulia = 0,      // quaternion Julia
+    kVarJulia = 0,      // quaternion Julia z^2 + c
     kVarBulbReal = 1,   // Mandelbulb, real power (trigonometric map)
     kVarBulbInt = 2,    // Mandelbulb, integer power read at run time
     kVarBulb8 = 3,      // Mandelbulb, power 8 fixed at compile time
-    kNumVariants = 4
+    kVarJuliaDeg = 4,   // quaternion Julia z^p + c, integer degree p >= 3 read at run time
+    kNumVariants = 5
 };
 
 // status byte
@@ -45,7 +46,7 @@ struct alignas(16) JobDev {
     float inv_w2, inv_h2;  // 2/W and 2/H
     int32_t width, height, tiles_x, tiles_y;
     // fractal
-    int32_t kind, int_power, max_iter, n_planes;
+    int32_t kind, int_power, max_iter, n_planes;   // int_power: Julia degree, integer Mandelbulb n, or 0
     float c[4];
     float power, n_rev, bailout2, radius;   // n_rev = n / (2 pi)
     // planes (unit normals)

@@ -34,8 +34,11 @@ hipError_t launch_distance(int variant, const OrbitParams& P, const float* pts, 
         case kVarBulbInt:
             hipLaunchKernelGGL(distance_kernel<BulbOrbit<-1>>, dim3(grid), dim3(block), 0, stream, P, pts, n, d, it);
             break;
-        default:
+        case kVarBulb8:
             hipLaunchKernelGGL(distance_kernel<BulbOrbit<8>>, dim3(grid), dim3(block), 0, stream, P, pts, n, d, it);
+            break;
+        default:
+            hipLaunchKernelGGL(distance_kernel<JuliaDegOrbit>, dim3(grid), dim3(block), 0, stream, P, pts, n, d, it);
             break;
     }
     return hipGetLastError();

@@ -44,6 +44,7 @@ template <> struct OrbitOf<kVarJulia> { using T = JuliaOrbit; };
 template <> struct OrbitOf<kVarBulbReal> { using T = BulbOrbit<0>; };
 template <> struct OrbitOf<kVarBulbInt> { using T = BulbOrbit<-1>; };
 template <> struct OrbitOf<kVarBulb8> { using T = BulbOrbit<8>; };
+template <> struct OrbitOf<kVarJuliaDeg> { using T = JuliaDegOrbit; };
 
 enum MarchPhase : int { kIdle = 0, kCut = 1, kMarch = 2, kRefine = 3, kDone = 4 };
 
@@ -526,7 +527,8 @@ static hipError_t launch_stage_var(int variant, int stage, const LaunchCfg& cfg,
         case kVarJulia: return launch_stage<kVarJulia, BATCH>(stage, cfg, jobs, job1, hdr, stream);
         case kVarBulbReal: return launch_stage<kVarBulbReal, BATCH>(stage, cfg, jobs, job1, hdr, stream);
         case kVarBulbInt: return launch_stage<kVarBulbInt, BATCH>(stage, cfg, jobs, job1, hdr, stream);
-        default: return launch_stage<kVarBulb8, BATCH>(stage, cfg, jobs, job1, hdr, stream);
+        case kVarBulb8: return launch_stage<kVarBulb8, BATCH>(stage, cfg, jobs, job1, hdr, stream);
+        default: return launch_stage<kVarJuliaDeg, BATCH>(stage, cfg, jobs, job1, hdr, stream);
     }
 }
 
@@ -540,7 +542,8 @@ const void* trace_kernel_symbol(int variant, bool batch) {
         case kVarJulia: return batch ? kernel_ptr<kVarJulia, true>() : kernel_ptr<kVarJulia, false>();
         case kVarBulbReal: return batch ? kernel_ptr<kVarBulbReal, true>() : kernel_ptr<kVarBulbReal, false>();
         case kVarBulbInt: return batch ? kernel_ptr<kVarBulbInt, true>() : kernel_ptr<kVarBulbInt, false>();
-        default: return batch ? kernel_ptr<kVarBulb8, true>() : kernel_ptr<kVarBulb8, false>();
+        case kVarBulb8: return batch ? kernel_ptr<kVarBulb8, true>() : kernel_ptr<kVarBulb8, false>();
+        default: return batch ? kernel_ptr<kVarJuliaDeg, true>() : kernel_ptr<kVarJuliaDeg, false>();
     }
 }
 

@@ -44,6 +44,11 @@ CASES = {
                                                               W.plane([-0.4, 1.0, 0.3], 0.3)]),
                                  [0, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12]),
     "julia_no_plane": (lambda: W.julia_view(width=64, height=64), [0, 1, 2, 3]),
+    # the cubic of Listing 4 and a degree-5 set (runtime-degree kernels)
+    "julia3_cut": (lambda: W.julia_view(c=W.JULIA_C3, degree=3, width=64, height=64,
+                                        planes=[W.plane([-0.2, 0.3, 1.0], 0.1)]), [0, 1, 2, 3, 5, 6, 7, 8]),
+    "julia5_no_plane": (lambda: W.julia_view(c=[-0.5, 0.3, 0.1, 0.0], degree=5, width=56, height=56, max_iter=9),
+                        [0, 1, 2, 3]),
     "bulb8_cut_shadow": (lambda: W.bulb_view(0.7, 0.2, width=64, height=64, shadow=True,
                                              planes=[W.plane([0.2, 1.0, 0.1], 0.1)]), [4, 5, 6, 7, 8]),
     "bulb8_two_planes_shadow": (lambda: W.bulb_view(0.7, 0.2, width=64, height=64, shadow=True,

@@ -1,0 +1,182 @@
+"""Quaternion Julia sets of higher degree, z^p + c with p = 3..16 (Eq. 3-4;
+Listing 4 is the cubic), traced by the runtime-degree kernel variant:
+full-image parity with the FP64 oracle on views that span several 8x8 tiles
+and ragged edges, the 32-job degree batch (alone and mixed with degree-2 and
+Mandelbulb jobs in one call), graph replay, and argument validation.
+"""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from parity import assert_parity, compare, neighbour_flags, sampled_compare, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def frt():
+    import paper_2102_01747_amd as m
+    m.lib()
+    return m
+
+
+def _gpu(frt, job):
+    fr = frt.render(job, "cuda", counters=True)
+    torch.cuda.synchronize()
+    return to_numpy(fr)
+
+
+def _full_parity(frt, orc, job):
+    g = _gpu(frt, job)
+    o = orc.render(job)
+    cam = job["camera"]
+    nd = neighbour_flags(o["status"].reshape(cam["height"], cam["width"])).ravel()
+    st = compare(orc, job, g, o, nd)
+    print("degree %d %dx%d" % (job["fractal"]["power"], cam["width"], cam["height"]), st, flush=True)
+    assert st["oracle_hits"] > 0
+    assert_parity(st)
+    return st
+
+
+def test_cubic_view_parity(frt, orc):
+    """The cubic of Listing 4, cut by a plane."""
+    _full_parity(frt, orc, W.julia_view(c=W.JULIA_C3, degree=3, planes=[W.plane([-0.2, 0.3, 1.0], 0.1)]))
+
+
+def test_cubic_no_plane_parity(frt, orc):
+    _full_parity(frt, orc, W.julia_view(c=W.JULIA_C3, degree=3, width=192, height=160))
+
+
+def test_degree4_two_planes_shadow_ragged(frt, orc):
+    job = W.julia_view(c=[0.3, 0.5, 0.0, 0.2], degree=4, width=250, height=190, shadow=True,
+                       planes=[W.plane([0.3, 0.2, 1.0], 0.05), W.plane([-1.0, 0.4, 0.2], 0.3)])
+    _full_parity(frt, orc, job)
+
+
+def test_degree6_central_normals(frt, orc):
+    job = W.julia_view(c=[-0.5, 0.3, 0.1, 0.0], degree=6, width=200, height=136, normal_mode="central",
+                       max_iter=9)
+    _full_parity(frt, orc, job)
+
+
+def test_degree16_small_bailout(frt, orc):
+    """The highest degree accepted; bailout2 = 64 keeps 64^16 within float."""
+    job = W.julia_view(c=[-0.2, 0.6, 0.2, 0.2], degree=16, width=96, height=96, max_iter=6)
+    job["fractal"]["bailout2"] = 64.0
+    _full_parity(frt, orc, job)
+
+
+@pytest.fixture(scope="module")
+def degree_jobs():
+    return W.julia_degree_batch()
+
+
+def test_degree_batch_parity_against_oracle(frt, orc, degree_jobs):
+    outs = frt.render_batch(degree_jobs, "cuda", counters=True)
+    torch.cuda.synchronize()
+    checked = 0
+    for k, (job, fr) in enumerate(zip(degree_jobs, outs)):
+        g = to_numpy(fr)
+        cam = job["camera"]
+        W_, H = cam["width"], cam["height"]
+        if W_ * H <= 256 * 256:
+            o = orc.render(job)
+            nd = neighbour_flags(o["status"].reshape(H, W_)).ravel()
+            st = compare(orc, job, g, o, nd)
+        else:
+            pix = W.stratified_pixels(W_, H, 8, seed=k)
+            st = sampled_compare(orc, job, g, pix)
+        if st["oracle_hits"] == 0 and st["gpu_hits"] == 0:
+            continue
+        assert_parity(st)
+        checked += 1
+    print("degree-batch jobs with hits compared:", checked)
+    assert checked >= 20
+
+
+def test_degree_batch_equals_one_by_one(frt, degree_jobs):
+    jobs = degree_jobs[:12]
+    outs = frt.render_batch(jobs, "cuda")
+    singles = [frt.render(j, "cuda") for j in jobs]
+    torch.cuda.synchronize()
+    for k, (a, b) in enumerate(zip(outs, singles)):
+        a, b = to_numpy(a), to_numpy(b)
+        same = np.mean((a["status"] == b["status"]) & (a["depth"] == b["depth"]))
+        assert same >= 0.9999, (k, same)
+
+
+def test_mixed_degree_batch(frt, orc):
+    """Degree 2, 3 and 5 Julia jobs and a Mandelbulb in one call: three
+    kernel groups share one workspace."""
+    jobs = [W.julia_view(width=96, height=80),
+            W.julia_view(c=W.JULIA_C3, degree=3, width=100, height=72, planes=[W.plane([0.3, 0.2, 1.0], 0.05)]),
+            W.bulb_view(0.3, 0.1, width=80, height=64),
+            W.julia_view(c=[-0.5, 0.3, 0.1, 0.0], degree=5, width=64, height=90, shadow=True),
+            W.julia_view(c=W.JULIA_C3, degree=3, width=40, height=40)]
+    outs = frt.render_batch(jobs, "cuda", counters=True)
+    torch.cuda.synchronize()
+    for job, fr in zip(jobs, outs):
+        g = to_numpy(fr)
+        o = orc.render(job)
+        cam = job["camera"]
+        nd = neighbour_flags(o["status"].reshape(cam["height"], cam["width"])).ravel()
+        st = compare(orc, job, g, o, nd)
+        assert_parity(st)
+
+
+def test_degree_graph_replay_matches_eager(frt, degree_jobs):
+    jobs = copy.deepcopy(degree_jobs[:8]) + [W.julia_view(width=64, height=64)]
+    frames = [frt.alloc_frame(j, "cuda") for j in jobs]
+    ref = [frt.alloc_frame(j, "cuda") for j in jobs]
+    ws = frt.alloc_workspace(len(jobs), "cuda")
+    frt.graph_reset()
+    rng = np.random.default_rng(9)
+    for rep in range(3):
+        if rep > 0:
+            for j in jobs:
+                j["fractal"]["c"] = W.f32v(np.array(j["fractal"]["c"]) + rng.normal(0, 0.01, 4))
+        frt.render_batch(jobs, "cuda", outs=frames, workspace=ws, use_graph=True)
+        junk = (torch.randn(1 << 20, device="cuda") * 2).sum()
+        torch.cuda.synchronize()
+        frt.render_batch(jobs, "cuda", outs=ref, workspace=frt.alloc_workspace(len(jobs), "cuda"))
+        torch.cuda.synchronize()
+        for a, b in zip(frames, ref):
+            a, b = to_numpy(a), to_numpy(b)
+            assert np.array_equal(a["status"], b["status"])
+            assert np.array_equal(a["depth"], b["depth"])
+            assert np.array_equal(a["colour"], b["colour"])
+    frt.graph_reset()
+    del junk
+
+
+def test_degree_batch_throughput(frt, degree_jobs):
+    frames = [frt.alloc_frame(j, "cuda") for j in degree_jobs]
+    ws = frt.alloc_workspace(len(degree_jobs), "cuda")
+    frt.render_batch(degree_jobs, "cuda", outs=frames, workspace=ws)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    reps = 5
+    for _ in range(reps):
+        frt.render_batch(degree_jobs, "cuda", outs=frames, workspace=ws)
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / reps
+    rays = sum(j["camera"]["width"] * j["camera"]["height"] for j in degree_jobs)
+    print("degree batch: %d renders, %.3f ms, %.0f Mrays/s" % (len(degree_jobs), ms, rays / (ms * 1e-3) / 1e6))
+
+
+@pytest.mark.parametrize("degree,bail", [(2.5, 256.0), (1.0, 256.0), (17.0, 4.0), (8.0, 1e5)])
+def test_invalid_degree_raises_and_writes_nothing(frt, degree, bail):
+    job = W.julia_view(width=16, height=16)
+    fr = frt.alloc_frame(job, "cuda")
+    fr["depth"].fill_(7.0)
+    job["fractal"]["power"] = degree
+    job["fractal"]["bailout2"] = bail
+    with pytest.raises(frt.FrtError, match="invalid argument"):
+        frt.render(job, "cuda", out=fr)
+    torch.cuda.synchronize()
+    assert torch.all(fr["depth"] == 7.0)

@@ -62,6 +62,8 @@ def test_hardware_log2_exp2_rsq_rcp(frt):
 
 FRACTALS = {
     "julia": W.julia(W.JULIA_C1, 11),
+    "julia3": W.julia(W.JULIA_C3, 11, degree=3),
+    "julia5": W.julia([-0.5, 0.3, 0.1, 0.0], 8, degree=5),
     "bulb8": W.bulb(8.0, 10),
     "bulb5": W.bulb(5.0, 10),
     "bulb_real": W.bulb(6.37, 10),

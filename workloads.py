@@ -31,6 +31,7 @@ ALBEDO = [1.0, 1.0, 1.0]
 K_AMBIENT = f32(0.1)
 K_DIFFUSE = f32(0.9)
 JULIA_C1 = f32v([-0.2, 0.6, 0.2, 0.2])     # quaternion constant of the Julia view
+JULIA_C3 = f32v([-0.45, 0.1, 0.4, 0.2])   # constant of the cubic (degree-3) Julia views
 
 
 def camera(eye, width, height, fov_y_deg=45.0, target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0)):
@@ -124,6 +125,30 @@ def julia_batch(seed=3, n_jobs=64, sizes=(128, 256, 512, 1024), max_steps=256):
         eps = rng.uniform(1e-4, 1e-3)
         jobs.append(julia_view(c=c, width=w, height=h, max_iter=iters, max_steps=max_steps, eps_abs=eps,
                                planes=[plane(nrm, 0.0)]))
+    return jobs
+
+
+# ---------------------------------------------------------------------------
+# Batch of 32 quaternion Julia renders of higher degree (seed 6; per job in
+# this order): degree p uniform in {3, 4, 5, 6}; c ~ U[-0.8, 0.8]^4; cut
+# plane through the origin with normal normalize(N(0, I3)); W and H drawn
+# independently from {256, 512, 1024}; iterations uniform in 8..16;
+# eps_abs ~ U[1e-4, 1e-3].  Camera and step budget as in the Julia view.
+# ---------------------------------------------------------------------------
+def julia_degree_batch(seed=6, n_jobs=32, degrees=(3, 4, 5, 6), sizes=(256, 512, 1024), max_steps=256):
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for _ in range(n_jobs):
+        p = int(rng.choice(degrees))
+        c = rng.uniform(-0.8, 0.8, size=4)
+        nrm = rng.normal(size=3)
+        nrm = nrm / np.linalg.norm(nrm)
+        w = int(rng.choice(sizes))
+        h = int(rng.choice(sizes))
+        iters = int(rng.integers(8, 17))
+        eps = rng.uniform(1e-4, 1e-3)
+        jobs.append(julia_view(c=c, width=w, height=h, max_iter=iters, max_steps=max_steps, eps_abs=eps,
+                               planes=[plane(nrm, 0.0)], degree=p))
     return jobs
 
 
