@@ -37,8 +37,10 @@
  *   R9  Hit depth is the root of d(o+t*dir) - eps(t) between the last two
  *       samples (the listing's lt/lh); here by bisection to the resolution
  *       of double precision.
- *   R10 Normals: tetrahedral taps of Eq. 5 with h = 0.5773 eps (Listing 5)
- *       or central differences with h = eps.
+ *   R10 Normals: tetrahedral taps of Eq. 5 with h = 0.5773 eps (Listing 5),
+ *       central differences with h = eps, or (mode 2) the analytic normal of
+ *       Sec. 2's quotient-rule remark: the exact gradient of the estimate d
+ *       at the hit point itself, by forward-mode differentiation.
  *   R11 Lambert shading with one optional shadow ray replaces the paper's
  *       Phong/Fresnel closest-hit shader.
  */
@@ -78,7 +80,7 @@ typedef struct {
 typedef struct {
     int32_t max_steps;
     double eps_abs, eps_rel, step_clamp, t_max;
-    int32_t normal_mode;   /* 0 tetrahedral (Eq. 5), 1 central differences */
+    int32_t normal_mode;   /* 0 tetrahedral (Eq. 5), 1 central differences, 2 analytic gradient */
     int32_t shadow;        /* 1: one shadow ray per lit hit                */
     double light[3], albedo[3], k_ambient, k_diffuse;
 } or_march;
@@ -238,6 +240,11 @@ static de_result fractal_de(const or_fractal* f, const double p[3]) {
     return f->kind == 0 ? julia_de(f, p) : bulb_de(f, p);
 }
 
+/* Gradient of the estimate at p (the analytic normal of R10), defined with
+ * the dual numbers further down.                                            */
+static int32_t analytic_gradient(const or_fractal* f, const double p[3], double rel, uint64_t seed, uint64_t key,
+                                 double g[3]);
+
 /* Escape count of the orbit at p with an explicit iteration budget (R5). */
 int32_t oracle_escape_iters(const or_fractal* f, const double p[3], int32_t max_iter) {
     or_fractal g = *f;
@@ -330,6 +337,8 @@ void oracle_normal_perturbed(const or_fractal* f, const double* pts, const doubl
                 double d = perturbed_de(f, q, rel, seed, (uint64_t)i * 8u + (uint64_t)a);
                 for (int k = 0; k < 3; ++k) g[k] += TETRA[a][k] * d;
             }
+        } else if (mode == 2) {
+            analytic_gradient(f, p, rel, seed, (uint64_t)i * 8u, g);
         } else {
             for (int k = 0; k < 3; ++k) {
                 double qp[3] = { p[0], p[1], p[2] }, qm[3] = { p[0], p[1], p[2] };
@@ -558,7 +567,8 @@ static double refine_root(const or_fractal* f, const double o[3], const double d
     return 0.5 * (a + b);
 }
 
-/* R10: normal at p from distance taps.  A zero gradient falls back to -dir. */
+/* R10: normal at p from distance taps, or the analytic gradient (mode 2).
+ * A zero gradient falls back to -dir.                                       */
 
 static void estimate_normal(const or_fractal* f, const double p[3], double eps, int mode,
                             const double dir[3], double nrm[3], int64_t* evals, int64_t* bodies) {
@@ -571,7 +581,7 @@ static void estimate_normal(const or_fractal* f, const double p[3], double eps, 
             (*evals)++; (*bodies) += r.bodies;
             for (int k = 0; k < 3; ++k) g[k] += TETRA[i][k] * r.d;
         }
-    } else {
+    } else if (mode == 1) {
         double h = eps;
         for (int k = 0; k < 3; ++k) {
             double qp[3] = { p[0], p[1], p[2] }, qm[3] = { p[0], p[1], p[2] };
@@ -580,9 +590,12 @@ static void estimate_normal(const or_fractal* f, const double p[3], double eps, 
             (*evals) += 2; (*bodies) += rp.bodies + rm.bodies;
             g[k] = rp.d - rm.d;
         }
+    } else {
+        int32_t it = analytic_gradient(f, p, 0.0, 0, 0, g);
+        (*evals) += 1; (*bodies) += it < f->max_iter ? it + 1 : it;
     }
     double l = sqrt(dot3(g, g));
-    if (l == 0.0) { nrm[0] = -dir[0]; nrm[1] = -dir[1]; nrm[2] = -dir[2]; return; }
+    if (!(l > 0.0 && isfinite(l))) { nrm[0] = -dir[0]; nrm[1] = -dir[1]; nrm[2] = -dir[2]; return; }
     nrm[0] = g[0] / l; nrm[1] = g[1] / l; nrm[2] = g[2] / l;
 }
 
@@ -794,8 +807,10 @@ static dual dqlen2(const dual z[4]) {
     return dadd(dadd(dmul(z[0], z[0]), dmul(z[1], z[1])), dadd(dmul(z[2], z[2]), dmul(z[3], z[3])));
 }
 
-/* Julia distance in dual arithmetic, same steps as julia_de. */
-static dual julia_de_dual(const or_fractal* f, const dual c[4], const dual p[3], int32_t* iters) {
+/* Julia distance in dual arithmetic, same steps as julia_de.  rel > 0
+ * applies the rounding probe of perturbed_de to every power z^p.            */
+static dual julia_de_dual(const or_fractal* f, const dual c[4], const dual p[3], int32_t* iters, double rel,
+                          uint64_t seed, uint64_t key) {
     dual z[4] = { p[0], p[1], p[2], dc(0.0) };
     dual dz2 = dc(1.0), m2 = dc(0.0);
     int32_t n = 0;
@@ -805,6 +820,8 @@ static dual julia_de_dual(const or_fractal* f, const dual c[4], const dual p[3],
         dquat_pow(z, deg - 1, zq);
         dz2 = dmul(dz2, dscale(dqlen2(zq), (double)deg * (double)deg));
         dquat_pow(z, deg, zp);
+        if (rel != 0.0)
+            for (int k = 0; k < 4; ++k) zp[k] = dscale(zp[k], noise(seed, key, i, k, rel));
         for (int k = 0; k < 4; ++k) z[k] = dadd(zp[k], c[k]);
         m2 = dqlen2(z);
         if (m2.v > f->bailout2) break;
@@ -815,8 +832,10 @@ static dual julia_de_dual(const or_fractal* f, const dual c[4], const dual p[3],
     return dmul(dscale(dlog(m2), 0.25), dsqrt(ddiv(m2, dz2)));
 }
 
-/* Mandelbulb distance in dual arithmetic, same steps as bulb_de. */
-static dual bulb_de_dual(const or_fractal* f, dual n, const dual p[3], int32_t* iters) {
+/* Mandelbulb distance in dual arithmetic, same steps as bulb_de (rel as
+ * for julia_de_dual, applied to every power w^n).                            */
+static dual bulb_de_dual(const or_fractal* f, dual n, const dual p[3], int32_t* iters, double rel, uint64_t seed,
+                         uint64_t key) {
     dual w[3] = { p[0], p[1], p[2] };
     dual m = dadd(dadd(dmul(w[0], w[0]), dmul(w[1], w[1])), dmul(w[2], w[2]));
     dual dr = dc(1.0);
@@ -837,9 +856,9 @@ static dual bulb_de_dual(const or_fractal* f, dual n, const dual p[3], int32_t* 
             dual a = dmul(n, datan2(w[0], w[2]));
             dual rn = dexp(dmul(n, lr));                       /* r^n */
             dual sb = dsin(b);
-            w[0] = dadd(dmul(rn, dmul(sb, dsin(a))), p[0]);
-            w[1] = dadd(dmul(rn, dcos(b)), p[1]);
-            w[2] = dadd(dmul(rn, dmul(sb, dcos(a))), p[2]);
+            dual wn[3] = { dmul(rn, dmul(sb, dsin(a))), dmul(rn, dcos(b)), dmul(rn, dmul(sb, dcos(a))) };
+            for (int k = 0; k < 3; ++k)
+                w[k] = dadd(rel != 0.0 ? dscale(wn[k], noise(seed, key, i, k, rel)) : wn[k], p[k]);
         }
         m = dadd(dadd(dmul(w[0], w[0]), dmul(w[1], w[1])), dmul(w[2], w[2]));
         if (m.v > f->bailout2) break;
@@ -854,9 +873,28 @@ static dual fractal_de_dual(const or_fractal* f, const dual p[3], int32_t* iters
     if (f->kind == 0) {
         dual c[4];
         for (int k = 0; k < 4; ++k) c[k] = dseed(f->c[k], k);
-        return julia_de_dual(f, c, p, iters);
+        return julia_de_dual(f, c, p, iters, 0.0, 0, 0);
     }
-    return bulb_de_dual(f, dseed(f->power, 4), p, iters);
+    return bulb_de_dual(f, dseed(f->power, 4), p, iters, 0.0, 0, 0);
+}
+
+/* Gradient of the estimate with respect to the point (R10, mode 2): dual
+ * numbers seeded on the three coordinates, the fractal parameters constant.
+ * Returns the escape count.                                                 */
+static int32_t analytic_gradient(const or_fractal* f, const double p[3], double rel, uint64_t seed, uint64_t key,
+                                 double g[3]) {
+    dual P[3] = { dseed(p[0], 0), dseed(p[1], 1), dseed(p[2], 2) };
+    int32_t it = 0;
+    dual d;
+    if (f->kind == 0) {
+        dual c[4];
+        for (int k = 0; k < 4; ++k) c[k] = dc(f->c[k]);
+        d = julia_de_dual(f, c, P, &it, rel, seed, key);
+    } else {
+        d = bulb_de_dual(f, dc(f->power), P, &it, rel, seed, key);
+    }
+    for (int k = 0; k < 3; ++k) g[k] = d.g[k];
+    return it;
 }
 
 /* Jacobian rows per pixel: 0 depth, 1-3 normal, 4-6 colour; 13 columns
@@ -868,6 +906,9 @@ int oracle_pixel_jacobian(const or_camera* cam, const or_fractal* f, const or_pl
                           const or_march* mc, const int64_t* pix, int64_t n, int32_t n_threads,
                           double* jac, int32_t* tap_iters) {
     if (!cam || !f || !mc || !pix) return -1;
+    /* the analytic normal's parameter derivative needs second derivatives of
+     * the estimate, which first-order dual numbers do not carry */
+    if (mc->normal_mode == 2) return -2;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 4)

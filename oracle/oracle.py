@@ -26,6 +26,8 @@ FLAG_SHADOWED = 8
 FLAG_UNREFINED = 16
 FLAG_JUMP = 32          # oracle only: the root bracket closed on a jump of the estimate
 
+NORMAL_MODES = {"tetra": 0, "central": 1, "analytic": 2}
+
 # Jacobian column slots (see oracle_pixel_jacobian)
 SLOT_C = slice(0, 4)
 SLOT_POWER = 4
@@ -125,7 +127,7 @@ def make_planes(planes):
 
 
 def make_march(m):
-    mode = {"tetra": 0, "central": 1}[m["normal_mode"]]
+    mode = NORMAL_MODES[m["normal_mode"]]
     return March(int(m["max_steps"]), float(m["eps_abs"]), float(m["eps_rel"]), float(m["step_clamp"]),
                  float(m["t_max"]), mode, int(bool(m["shadow"])), c_double3(*m["light_dir"]),
                  c_double3(*m["albedo"]), float(m["k_ambient"]), float(m["k_diffuse"]))
@@ -182,6 +184,8 @@ def pixel_jacobian(job, pixels, threads=0):
     rc = L.oracle_pixel_jacobian(ctypes.byref(cam), ctypes.byref(fr), pl, npl, ctypes.byref(mc),
                                  _ptr(pix, ctypes.c_int64), n, int(threads),
                                  _ptr(jac, ctypes.c_double), _ptr(taps, ctypes.c_int32))
+    if rc == -2:
+        raise NotImplementedError("the Jacobian of analytic normals needs second derivatives")
     if rc != 0:
         raise RuntimeError("oracle_pixel_jacobian failed")
     return jac, taps
@@ -266,7 +270,7 @@ def normal_at(fractal, points, dirs, eps, mode):
     drs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
     ep = np.ascontiguousarray(np.broadcast_to(eps, (pts.shape[0],)), dtype=np.float64)
     out = np.empty_like(pts)
-    m = {"tetra": 0, "central": 1}[mode] if isinstance(mode, str) else int(mode)
+    m = NORMAL_MODES[mode] if isinstance(mode, str) else int(mode)
     L.oracle_normal_at(ctypes.byref(fr), _ptr(pts, ctypes.c_double), _ptr(drs, ctypes.c_double),
                        _ptr(ep, ctypes.c_double), pts.shape[0], m, _ptr(out, ctypes.c_double))
     return out
@@ -291,7 +295,9 @@ CENTRAL_TAPS = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1]
 
 def tap_points(points, eps, mode):
     """Normal-tap positions [n, taps, 3] around points [n,3] for per-point eps."""
-    m = {"tetra": 0, "central": 1}[mode] if isinstance(mode, str) else int(mode)
+    m = NORMAL_MODES[mode] if isinstance(mode, str) else int(mode)
+    if m == 2:      # the analytic normal evaluates the estimate at the point itself
+        return np.array(points, dtype=np.float64)[:, None, :]
     taps, h = (TETRA_TAPS, 0.5773 * np.asarray(eps)) if m == 0 else (CENTRAL_TAPS, np.asarray(eps))
     return np.asarray(points)[:, None, :] + np.asarray(h).reshape(-1, 1, 1) * taps[None]
 
@@ -305,7 +311,7 @@ def normal_perturbed(fractal, points, dirs, eps, mode, rel, seed):
     drs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
     ep = np.ascontiguousarray(np.broadcast_to(eps, (pts.shape[0],)), dtype=np.float64)
     out = np.empty_like(pts)
-    m = {"tetra": 0, "central": 1}[mode] if isinstance(mode, str) else int(mode)
+    m = NORMAL_MODES[mode] if isinstance(mode, str) else int(mode)
     L.oracle_normal_perturbed(ctypes.byref(fr), _ptr(pts, ctypes.c_double), _ptr(drs, ctypes.c_double),
                               _ptr(ep, ctypes.c_double), pts.shape[0], m, float(rel), int(seed),
                               _ptr(out, ctypes.c_double))

@@ -119,7 +119,7 @@ def normal_ill_conditioned(orc, fr, mc, pts, dirs, eps, seeds=4, tol=2e-4, margi
     mg, esc = orc.escape_margin(fr, tp.reshape(-1, 3))
     ntap = tp.shape[1]
     ill = ~esc.reshape(-1, ntap).all(1) | (mg.reshape(-1, ntap).min(1) < margin)
-    p = fr["power"] if fr["kind"] == "bulb" else 2.0
+    p = fr["power"]          # Mandelbulb n, or the Julia degree
     ref = orc.normal_at(fr, pts, dirs, eps, mc["normal_mode"])
     for s in range(seeds):
         pert = orc.normal_perturbed(fr, pts, dirs, eps, mc["normal_mode"], 2.0 * p * 2.0 ** -24, 1000 + s)
