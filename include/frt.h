@@ -67,7 +67,7 @@ typedef enum {
 } frt_status;
 
 enum { FRT_JULIA = 0, FRT_MANDELBULB = 1 };
-enum { FRT_NORMAL_TETRA = 0, FRT_NORMAL_CENTRAL = 1 };
+enum { FRT_NORMAL_TETRA = 0, FRT_NORMAL_CENTRAL = 1, FRT_NORMAL_ANALYTIC = 2 };
 
 /* Pinhole camera: vertical field of view, pixel centres, row 0 at the top.
  * Ray through pixel (i, j): dir = normalize(f + x r + y u) with
@@ -115,7 +115,10 @@ typedef struct {
  * eps(t)/32) and one secant step on the final bracket; bisection picks the
  * same root as the FP64 reference when the bracket holds several (the
  * estimate jumps where the escape count changes).  Normals: tetrahedral taps with
- * h = 0.5773 eps(t*) or central differences with h = eps(t*).
+ * h = 0.5773 eps(t*), central differences with h = eps(t*), or the analytic
+ * normal: the exact gradient of the estimate at p* by forward-mode
+ * differentiation of the orbit (Sec. 2: on the set it is grad G / |grad G|),
+ * one orbit evaluation with three tangents and no tap spacing.
  * colour = albedo (k_ambient + k_diffuse max(0, N.L) V), L = light_dir
  * normalised, V = 0 when the shadow ray (from p* + 4 eps(t*) N toward L,
  * threshold eps(t*)) hits, else 1; V is traced only when shadow != 0 and
@@ -125,7 +128,7 @@ typedef struct {
     float eps_abs, eps_rel;     /* >= 0, not both 0                          */
     float step_clamp;           /* > 0                                       */
     float t_max;                /* > eps_abs                                 */
-    int32_t normal_mode;        /* FRT_NORMAL_TETRA or FRT_NORMAL_CENTRAL    */
+    int32_t normal_mode;        /* FRT_NORMAL_TETRA, _CENTRAL or _ANALYTIC   */
     int32_t refine_iters;       /* [0, 32]                                   */
     int32_t shadow;             /* 0 or 1                                    */
     float light_dir[3];         /* non-zero                                  */
@@ -211,7 +214,9 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
  * workspace: frt_workspace_bytes(n_jobs) bytes, not shared with a call in
  *       flight on another stream.
  * Errors: as frt_render_batch (validation before any launch, no writes);
- * FRT_EINVAL also for a null gradient output or a null depth / status.     */
+ * FRT_EINVAL also for a null gradient output or a null depth / status;
+ * FRT_EUNSUPPORTED for a job with analytic normals (their parameter
+ * derivative needs second derivatives of the estimate, not provided).      */
 frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float* const* g_colour,
                                const float* const* g_depth, const float* const* g_normal,
                                float* const* grad_pixel, float* grad_c, float* grad_power, float* grad_plane,
@@ -223,6 +228,17 @@ frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float*
  * no escape).  frac is validated as for frt_render.                        */
 frt_status frt_distance(const frt_fractal* frac, const float* points, int64_t n, float* d, int32_t* iters,
                         void* stream);
+
+/* Normal at n points by the renderer's rule for normal_mode (the normal
+ * stage of Eq. 5 / Listing 5, or the analytic gradient of Sec. 2's remark,
+ * without the march): points float[n][3] (device); eps float[n] (device)
+ * the tap scale eps(t*) as in frt_march, ignored by FRT_NORMAL_ANALYTIC and
+ * then allowed to be NULL; normals float[n][3] (device) receives unit
+ * normals, (0, 0, 0) where the gradient is zero or not finite.  frac is
+ * validated as for frt_render; FRT_EINVAL for an unknown mode or a NULL eps
+ * with a tap mode.                                                          */
+frt_status frt_normal_at(const frt_fractal* frac, int32_t normal_mode, const float* points, const float* eps,
+                         int64_t n, float* normals, void* stream);
 
 /* Evaluate one of the library's fast float32 functions on n device values,
  * for accuracy checks: func 0 acos(x) (x clamped to [-1, 1]), 1 atan2(x, y),

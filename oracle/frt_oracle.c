@@ -722,6 +722,44 @@ int32_t oracle_max_threads(void) {
 #endif
 }
 
+/* Final march bracket of listed pixels (R9): for a refinable surface hit the
+ * last two samples [lt, t] and the number of sign changes of
+ * g(s) = d(o + s dir) - eps(s) over `samples` + 1 uniform points of it.
+ * More than one crossing means the bracket holds several correct depths
+ * (a chaotic layer of the estimate); other pixels report lt = t = -1 and 0. */
+int oracle_bracket_crossings(const or_camera* cam, const or_fractal* f, const or_plane* planes, int32_t n_planes,
+                             const or_march* mc, const int64_t* pix, int64_t n, int32_t samples, double* lt,
+                             double* t, int32_t* crossings) {
+    if (!cam || !f || !mc || !pix || samples < 1) return -1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (int64_t q = 0; q < n; ++q) {
+        int32_t i = (int32_t)(pix[q] % cam->width), j = (int32_t)(pix[q] / cam->width);
+        double o[3], dir[3];
+        oracle_camera_ray(cam, i, j, o, dir);
+        trace_result tr;
+        trace_ray(f, planes, n_planes, o, dir, mc->eps_abs, mc->eps_rel, mc->eps_abs, mc->max_steps,
+                  mc->step_clamp, mc->t_max, &tr);
+        lt[q] = t[q] = -1.0;
+        crossings[q] = 0;
+        if (tr.status != ST_HIT || !tr.has_prev) continue;
+        lt[q] = tr.lt;
+        t[q] = tr.t;
+        int count = 0, prev_sign = 0;
+        for (int32_t k = 0; k <= samples; ++k) {
+            double s = tr.lt + (tr.t - tr.lt) * (double)k / (double)samples;
+            double pt[3] = { o[0] + s * dir[0], o[1] + s * dir[1], o[2] + s * dir[2] };
+            double g = fractal_de(f, pt).d - (mc->eps_abs + mc->eps_rel * s);
+            int sg = g < 0.0 ? -1 : 1;
+            if (k > 0 && sg != prev_sign) ++count;
+            prev_sign = sg;
+        }
+        crossings[q] = count;
+    }
+    return 0;
+}
+
 /* ======================================================================== */
 /* Gradients by forward-mode automatic differentiation (dual numbers).       */
 /*                                                                           */

@@ -90,6 +90,10 @@ def lib():
                                             dp, P(ctypes.c_int32)]
         L.oracle_pixel_jacobian.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int32
+        L.oracle_bracket_crossings.argtypes = [P(Camera), P(Fractal), P(Plane), ctypes.c_int32, P(March),
+                                               P(ctypes.c_int64), ctypes.c_int64, ctypes.c_int32, dp, dp,
+                                               P(ctypes.c_int32)]
+        L.oracle_bracket_crossings.restype = ctypes.c_int
         L.oracle_escape_margin.argtypes = [P(Fractal), dp, ctypes.c_int64, dp, P(ctypes.c_int32)]
         L.oracle_normal_perturbed.argtypes = [P(Fractal), dp, dp, dp, ctypes.c_int64, ctypes.c_int32,
                                               ctypes.c_double, ctypes.c_uint64, dp]
@@ -189,6 +193,25 @@ def pixel_jacobian(job, pixels, threads=0):
     if rc != 0:
         raise RuntimeError("oracle_pixel_jacobian failed")
     return jac, taps
+
+
+def bracket_crossings(job, pixels, samples=256):
+    """Final march bracket (lt, t) of listed pixels and the number of sign
+    changes of d - eps over `samples` + 1 uniform points of it (-1, -1, 0
+    where the ray did not end on a refinable surface hit)."""
+    L = lib()
+    cam, fr, mc = make_camera(job["camera"]), make_fractal(job["fractal"]), make_march(job["march"])
+    pl, npl = make_planes(job.get("planes", []))
+    pix = np.ascontiguousarray(pixels, dtype=np.int64)
+    n = pix.size
+    lt, t = np.empty(n), np.empty(n)
+    cr = np.empty(n, np.int32)
+    rc = L.oracle_bracket_crossings(ctypes.byref(cam), ctypes.byref(fr), pl, npl, ctypes.byref(mc),
+                                    _ptr(pix, ctypes.c_int64), n, int(samples), _ptr(lt, ctypes.c_double),
+                                    _ptr(t, ctypes.c_double), _ptr(cr, ctypes.c_int32))
+    if rc != 0:
+        raise RuntimeError("oracle_bracket_crossings failed")
+    return lt, t, cr
 
 
 def de(fractal, points):

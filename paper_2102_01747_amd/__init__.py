@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libfrt.so")
 FRT_OK, FRT_EINVAL, FRT_EHIP, FRT_ENOMEM, FRT_EUNSUPPORTED = 0, -1, -2, -3, -4
 STATUS_MISS_BOUNDS, STATUS_MISS_TMAX, STATUS_HIT, STATUS_HIT_CUT, STATUS_HIT_EXHAUSTED = 0, 1, 2, 3, 4
 FLAG_SHADOWED, FLAG_UNREFINED, FLAG_SHADOW_RAY = 8, 16, 64
+NORMAL_MODES = {"tetra": 0, "central": 1, "analytic": 2}
 VARIANTS = {"julia": 0, "bulb_real": 1, "bulb_int": 2, "bulb8": 3, "julia_deg": 4}
 
 f3 = ctypes.c_float * 3
@@ -89,6 +90,8 @@ def lib():
         L.frt_graph_reset.restype = ctypes.c_int
         L.frt_distance.argtypes = [P(Fractal), vp, ctypes.c_int64, vp, vp, vp]
         L.frt_distance.restype = ctypes.c_int
+        L.frt_normal_at.argtypes = [P(Fractal), i32, vp, vp, ctypes.c_int64, vp, vp]
+        L.frt_normal_at.restype = ctypes.c_int
         L.frt_math_eval.argtypes = [i32, vp, vp, vp, ctypes.c_int64, vp]
         L.frt_math_eval.restype = ctypes.c_int
         L.frt_set_stage_timing.argtypes = [i32]
@@ -149,7 +152,7 @@ def make_planes(planes):
 
 
 def make_march(m):
-    mode = {"tetra": 0, "central": 1}[m["normal_mode"]] if isinstance(m["normal_mode"], str) else int(m["normal_mode"])
+    mode = NORMAL_MODES[m["normal_mode"]] if isinstance(m["normal_mode"], str) else int(m["normal_mode"])
     return March(int(m["max_steps"]), float(m["eps_abs"]), float(m["eps_rel"]), float(m["step_clamp"]),
                  float(m["t_max"]), mode, int(m.get("refine_iters", 12)), int(bool(m["shadow"])),
                  f3(*m["light_dir"]), f3(*m["albedo"]), float(m["k_ambient"]), float(m["k_diffuse"]))
@@ -292,6 +295,24 @@ def distance(fractal, points, device="cuda"):
     frac = make_fractal(fractal)
     _check(lib().frt_distance(ctypes.byref(frac), _ptr(pts), n, _ptr(d), _ptr(it), _stream(dev)))
     return d, it
+
+
+def normal_at(fractal, points, mode, eps=None, device="cuda"):
+    """Unit normals [n, 3] at points [n, 3] by the renderer's rule for `mode`
+    ("tetra", "central" with tap scale eps [n]; "analytic"); zero where the
+    gradient vanishes."""
+    dev = _device(device)
+    pts = torch.as_tensor(points, dtype=torch.float32, device=dev).reshape(-1, 3).contiguous()
+    n = pts.shape[0]
+    m = NORMAL_MODES[mode] if isinstance(mode, str) else int(mode)
+    ep = None if eps is None else torch.as_tensor(eps, dtype=torch.float32, device=dev).reshape(-1).contiguous()
+    if ep is not None and ep.numel() != n:
+        raise ValueError("eps must hold one value per point")
+    out = torch.empty(n, 3, device=dev, dtype=torch.float32)
+    frac = make_fractal(fractal)
+    _check(lib().frt_normal_at(ctypes.byref(frac), m, _ptr(pts), _ptr(ep) if ep is not None else None, n, _ptr(out),
+                               _stream(dev)))
+    return out
 
 
 MATH_FUNCS = {"acos": 0, "atan2": 1, "sin_rev": 2, "cos_rev": 3, "log2": 4, "exp2": 5, "rsq": 6, "rcp": 7}

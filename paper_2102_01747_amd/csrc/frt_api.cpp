@@ -197,7 +197,8 @@ bool validate(const frt_camera* cam, const frt_fractal* fr, const frt_plane* pla
     }
     if (!(mc->step_clamp > 0.0f)) { why = "step_clamp must be > 0"; return false; }
     if (!(mc->t_max > mc->eps_abs)) { why = "t_max must exceed eps_abs"; return false; }
-    if (mc->normal_mode != FRT_NORMAL_TETRA && mc->normal_mode != FRT_NORMAL_CENTRAL) {
+    if (mc->normal_mode != FRT_NORMAL_TETRA && mc->normal_mode != FRT_NORMAL_CENTRAL &&
+        mc->normal_mode != FRT_NORMAL_ANALYTIC) {
         why = "unknown normal_mode"; return false;
     }
     if (mc->refine_iters < 0 || mc->refine_iters > 32) { why = "refine_iters must be in [0, 32]"; return false; }
@@ -524,13 +525,9 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
     return FRT_OK;
 }
 
-frt_status frt_distance(const frt_fractal* frac, const float* points, int64_t n, float* d, int32_t* iters,
-                        void* stream) {
-    g_last_error.clear();
-    if (!frac) return fail(FRT_EINVAL, "null fractal");
-    if (n < 0) return fail(FRT_EINVAL, "n must be >= 0");
-    if (n == 0) return FRT_OK;
-    if (!points || !d) return fail(FRT_EINVAL, "null points or output");
+// Orbit parameters and kernel variant of a fractal for the point queries
+// (validated with a placeholder camera and march).
+static bool query_params(const frt_fractal* frac, frt::OrbitParams& P, int& variant, std::string& why) {
     frt_camera cam{};
     cam.eye[2] = 1.0f;
     cam.up[1] = 1.0f;
@@ -542,12 +539,10 @@ frt_status frt_distance(const frt_fractal* frac, const float* points, int64_t n,
     mc.step_clamp = 1.0f;
     mc.t_max = 2.0f;
     mc.light_dir[1] = 1.0f;
-    std::string why;
-    if (!validate(&cam, frac, nullptr, 0, &mc, nullptr, false, why)) return fail(FRT_EINVAL, why);
+    if (!validate(&cam, frac, nullptr, 0, &mc, nullptr, false, why)) return false;
     frt_frame none{};
     JobDev J;
     pack(&cam, frac, nullptr, 0, &mc, none, 0, J);
-    frt::OrbitParams P;
     P.c0 = J.c[0]; P.c1 = J.c[1]; P.c2 = J.c[2]; P.c3 = J.c[3];
     P.n = J.power;
     P.nm1_half = 0.5f * (J.power - 1.0f);
@@ -556,8 +551,43 @@ frt_status frt_distance(const frt_fractal* frac, const float* points, int64_t n,
     P.kind = J.kind;
     P.max_iter = J.max_iter;
     P.bail2 = J.bailout2;
-    hipError_t e = frt::launch_distance(variant_of(J), P, points, n, d, iters, static_cast<hipStream_t>(stream));
+    variant = variant_of(J);
+    return true;
+}
+
+frt_status frt_distance(const frt_fractal* frac, const float* points, int64_t n, float* d, int32_t* iters,
+                        void* stream) {
+    g_last_error.clear();
+    if (!frac) return fail(FRT_EINVAL, "null fractal");
+    if (n < 0) return fail(FRT_EINVAL, "n must be >= 0");
+    if (n == 0) return FRT_OK;
+    if (!points || !d) return fail(FRT_EINVAL, "null points or output");
+    std::string why;
+    frt::OrbitParams P;
+    int variant = 0;
+    if (!query_params(frac, P, variant, why)) return fail(FRT_EINVAL, why);
+    hipError_t e = frt::launch_distance(variant, P, points, n, d, iters, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "distance launch");
+    return FRT_OK;
+}
+
+frt_status frt_normal_at(const frt_fractal* frac, int32_t normal_mode, const float* points, const float* eps,
+                         int64_t n, float* normals, void* stream) {
+    g_last_error.clear();
+    if (!frac) return fail(FRT_EINVAL, "null fractal");
+    if (normal_mode != FRT_NORMAL_TETRA && normal_mode != FRT_NORMAL_CENTRAL && normal_mode != FRT_NORMAL_ANALYTIC)
+        return fail(FRT_EINVAL, "unknown normal_mode");
+    if (n < 0) return fail(FRT_EINVAL, "n must be >= 0");
+    if (n == 0) return FRT_OK;
+    if (!points || !normals) return fail(FRT_EINVAL, "null points or output");
+    if (!eps && normal_mode != FRT_NORMAL_ANALYTIC) return fail(FRT_EINVAL, "the tap modes need eps");
+    std::string why;
+    frt::OrbitParams P;
+    int variant = 0;
+    if (!query_params(frac, P, variant, why)) return fail(FRT_EINVAL, why);
+    hipError_t e = frt::launch_normal_query(variant, P, normal_mode, points, eps, n, normals,
+                                            static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "normal launch");
     return FRT_OK;
 }
 
@@ -592,6 +622,9 @@ frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float*
             return fail(FRT_EINVAL, "job " + std::to_string(i) + ": " + why);
         if (!jb.out.depth || !jb.out.status)
             return fail(FRT_EINVAL, "job " + std::to_string(i) + ": null depth or status plane");
+        if (jb.march.normal_mode == FRT_NORMAL_ANALYTIC)
+            return fail(FRT_EUNSUPPORTED, "job " + std::to_string(i) +
+                                              ": the adjoint of analytic normals needs second derivatives");
         pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, begin, table[size_t(i)]);
         begin += table[size_t(i)].ray_count;
         frt::AdjointJob& a = adj[size_t(i)];

@@ -39,6 +39,10 @@ const void* trace_kernel_symbol(int variant, bool batch);
 struct OrbitParams;
 hipError_t launch_distance(int variant, const OrbitParams& P, const float* pts, long long n, float* d, int* it,
                            hipStream_t stream);
+// Unit normals at n points by the renderer's rule for `mode` ((0, 0, 0) for
+// a zero or non-finite gradient).
+hipError_t launch_normal_query(int variant, const OrbitParams& P, int mode, const float* pts, const float* eps,
+                               long long n, float* out, hipStream_t stream);
 hipError_t launch_math(int func, const float* x, const float* y, float* out, long long n, hipStream_t stream);
 
 // Adjoint over the hit pixels of a batch (frt_adjoint.hip): zeroes the

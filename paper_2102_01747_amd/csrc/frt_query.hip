@@ -1,11 +1,13 @@
-// frt_query.hip -- point queries: the distance estimate at arbitrary points
-// (the same orbit code the renderer marches with) and an evaluator of the
-// library's fast float32 transcendentals, for accuracy checks.
+// frt_query.hip -- point queries: the distance estimate and the normal at
+// arbitrary points (the same orbit and normal code the renderer uses) and an
+// evaluator of the library's fast float32 transcendentals, for accuracy
+// checks.
 #include <hip/hip_runtime.h>
 
 #include "frt_fractal.hpp"
 #include "frt_internal.hpp"
 #include "frt_job.hpp"
+#include "frt_normal.hpp"
 
 namespace frt {
 
@@ -39,6 +41,51 @@ hipError_t launch_distance(int variant, const OrbitParams& P, const float* pts, 
             break;
         default:
             hipLaunchKernelGGL(distance_kernel<JuliaDegOrbit>, dim3(grid), dim3(block), 0, stream, P, pts, n, d, it);
+            break;
+    }
+    return hipGetLastError();
+}
+
+template <int VAR>
+__global__ void __launch_bounds__(256) normal_query_kernel(OrbitParams P, int mode, const float* __restrict__ pts,
+                                                           const float* __restrict__ eps, long long n,
+                                                           float* __restrict__ out) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gx, gy, gz, nx = 0.0f, ny = 0.0f, nz = 0.0f;
+    unsigned evals, bodies;
+    estimate_normal<VAR>(P, mode, pts[3 * i], pts[3 * i + 1], pts[3 * i + 2], eps ? eps[i] : 0.0f, gx, gy, gz,
+                         evals, bodies);
+    if (!unit_normal(gx, gy, gz, nx, ny, nz)) nx = ny = nz = 0.0f;
+    out[3 * i] = nx;
+    out[3 * i + 1] = ny;
+    out[3 * i + 2] = nz;
+}
+
+hipError_t launch_normal_query(int variant, const OrbitParams& P, int mode, const float* pts, const float* eps,
+                               long long n, float* out, hipStream_t stream) {
+    const int block = 256;
+    const long long grid = (n + block - 1) / block;
+    switch (variant) {
+        case kVarJulia:
+            hipLaunchKernelGGL(normal_query_kernel<kVarJulia>, dim3(grid), dim3(block), 0, stream, P, mode, pts, eps,
+                               n, out);
+            break;
+        case kVarBulbReal:
+            hipLaunchKernelGGL(normal_query_kernel<kVarBulbReal>, dim3(grid), dim3(block), 0, stream, P, mode, pts,
+                               eps, n, out);
+            break;
+        case kVarBulbInt:
+            hipLaunchKernelGGL(normal_query_kernel<kVarBulbInt>, dim3(grid), dim3(block), 0, stream, P, mode, pts,
+                               eps, n, out);
+            break;
+        case kVarBulb8:
+            hipLaunchKernelGGL(normal_query_kernel<kVarBulb8>, dim3(grid), dim3(block), 0, stream, P, mode, pts, eps,
+                               n, out);
+            break;
+        default:
+            hipLaunchKernelGGL(normal_query_kernel<kVarJuliaDeg>, dim3(grid), dim3(block), 0, stream, P, mode, pts,
+                               eps, n, out);
             break;
     }
     return hipGetLastError();

@@ -27,6 +27,7 @@
 #include "frt_fractal.hpp"
 #include "frt_internal.hpp"
 #include "frt_job.hpp"
+#include "frt_normal.hpp"
 #include "frt_ray.hpp"
 
 namespace frt {
@@ -38,13 +39,6 @@ namespace frt {
 constexpr float kRefineTol = 1.0f / 32.0f;
 // Upper bound on orbit bodies per loop trip (keeps finished rays flowing).
 constexpr int kMaxBodiesPerTrip = 64;
-
-template <int VAR> struct OrbitOf;
-template <> struct OrbitOf<kVarJulia> { using T = JuliaOrbit; };
-template <> struct OrbitOf<kVarBulbReal> { using T = BulbOrbit<0>; };
-template <> struct OrbitOf<kVarBulbInt> { using T = BulbOrbit<-1>; };
-template <> struct OrbitOf<kVarBulb8> { using T = BulbOrbit<8>; };
-template <> struct OrbitOf<kVarJuliaDeg> { using T = JuliaDegOrbit; };
 
 enum MarchPhase : int { kIdle = 0, kCut = 1, kMarch = 2, kRefine = 3, kDone = 4 };
 
@@ -401,14 +395,14 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
 // ---------------------------------------------------------------------------
 // Normal taps (Eq. 5 / Listing 5) and Lambert shading of every hit, one lane
 // per ray of the batch.  Tetrahedral: h = 0.5773 eps(t*), N ~ sum nu_i d(p +
-// h nu_i); central: h = eps(t*), N_k ~ d(p + h e_k) - d(p - h e_k).  A zero
-// gradient falls back to -dir.  Colour assumes the point is lit; the shadow
+// h nu_i); central: h = eps(t*), N_k ~ d(p + h e_k) - d(p - h e_k); analytic:
+// N ~ grad d(p) by forward-mode tangents (frt_gradient.hpp).  A zero or
+// non-finite gradient falls back to -dir.  Colour assumes the point is lit; the shadow
 // kernel darkens shadowed pixels.
 // ---------------------------------------------------------------------------
 template <int VAR, bool BATCH>
 __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                                                      WorkspaceHeader* __restrict__ hdr) {
-    using Orbit = typename OrbitOf<VAR>::T;
     int n_jobs = 1;
     unsigned long long r_begin = 0, r_end = static_cast<unsigned long long>(job1.ray_count);
     if constexpr (BATCH) {
@@ -434,46 +428,14 @@ __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ 
             nz = J.normal[2 * NP + p];
         } else {
             const OrbitParams P = orbit_params(J);
-            Orbit orb;
             float dx, dy, dz;
             primary_dir(J, px, py, dx, dy, dz);
             const float ts = J.depth[p];
             const float eps = fmaf(J.eps_rel, ts, J.eps_abs);
             const float sx = fmaf(ts, dx, J.eye[0]), sy = fmaf(ts, dy, J.eye[1]), sz = fmaf(ts, dz, J.eye[2]);
-            float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-            if (J.normal_mode == 0) {
-                const float h = 0.5773f * eps;
-                for (int k = 0; k < 4; ++k) {
-                    const float vx = (k == 0 || k == 3) ? 1.0f : -1.0f;
-                    const float vy = (k >= 2) ? 1.0f : -1.0f;
-                    const float vz = (k == 1 || k == 3) ? 1.0f : -1.0f;
-                    const DEResult r = de_once(orb, P, fmaf(h, vx, sx), fmaf(h, vy, sy), fmaf(h, vz, sz));
-                    gx = fmaf(vx, r.d, gx);
-                    gy = fmaf(vy, r.d, gy);
-                    gz = fmaf(vz, r.d, gz);
-                    bodies += static_cast<unsigned>(r.bodies);
-                }
-                evals = 4;
-            } else {
-                const float h = eps;
-                for (int k = 0; k < 6; ++k) {
-                    const float sg = (k & 1) ? -h : h;
-                    const int ax = k >> 1;
-                    const DEResult r = de_once(orb, P, ax == 0 ? sx + sg : sx, ax == 1 ? sy + sg : sy,
-                                               ax == 2 ? sz + sg : sz);
-                    const float sd = (k & 1) ? -r.d : r.d;
-                    if (ax == 0) gx += sd; else if (ax == 1) gy += sd; else gz += sd;
-                    bodies += static_cast<unsigned>(r.bodies);
-                }
-                evals = 6;
-            }
-            const float gl2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
-            if (gl2 > 0.0f) {
-                const float inv = rsqrtf(gl2);
-                nx = gx * inv;
-                ny = gy * inv;
-                nz = gz * inv;
-            } else {
+            float gx, gy, gz;
+            estimate_normal<VAR>(P, J.normal_mode, sx, sy, sz, eps, gx, gy, gz, evals, bodies);
+            if (!unit_normal(gx, gy, gz, nx, ny, nz)) {
                 nx = -dx;
                 ny = -dy;
                 nz = -dz;

@@ -96,3 +96,34 @@ def test_distance_matches_oracle(frt, orc, name):
           "rel err p50 %.2e p99 %.2e p99.9 %.2e" % tuple(q))
     assert same[clean].mean() > 0.9999
     assert q[0] < 1e-6 and q[1] < 2e-3
+
+
+@pytest.mark.parametrize("mode", ["tetra", "central", "analytic"])
+@pytest.mark.parametrize("name", sorted(FRACTALS))
+def test_normal_query_matches_oracle(frt, orc, name, mode):
+    """The renderer's normal rule at points near the set (on rays toward the
+    origin, where the orbit escapes, with a tap scale of 1e-3), against the
+    oracle's normal at the same float32 points, on the points whose normal
+    is well conditioned at float32 resolution."""
+    from parity import angle, normal_ill_conditioned
+    fr = FRACTALS[name]
+    rng = np.random.default_rng(7)
+    R = orc.bound_radius(fr)
+    dirs = rng.normal(size=(4000, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    pts = (dirs * R * rng.uniform(0.5, 1.0, size=(4000, 1))).astype(np.float32)
+    d, _, _, _ = orc.de(fr, pts.astype(np.float64))
+    keep = (d > 2e-3) & (d < 0.05)           # near the set, outside the tap spacing
+    pts, dirs = pts[keep], dirs[keep]
+    eps = np.full(len(pts), 1e-3)
+    g = frt.normal_at(fr, pts, mode, eps=eps.astype(np.float32)).cpu().numpy()
+    p64 = pts.astype(np.float64)
+    ref = orc.normal_at(fr, p64, -dirs, eps, mode)
+    ill = normal_ill_conditioned(orc, fr, {"normal_mode": mode}, p64, -dirs, eps)
+    ok = ~ill & (np.linalg.norm(g, axis=1) > 0)
+    ang = angle(g[ok], ref[ok])
+    q = np.percentile(ang, [50, 99, 100])
+    print(name, mode, "points %d (well conditioned %d)" % (len(pts), ok.sum()),
+          "angle p50 %.2e p99 %.2e max %.2e" % tuple(q))
+    assert ok.sum() > 200
+    assert np.mean(ang <= 1e-3) >= 0.999 and q[1] < 3e-4

@@ -369,6 +369,19 @@ def test_c0_ball_hit_depth_normal_colour(orc, normal_mode):
     assert np.all(out["depth"][miss] == -1.0) and np.all(out["colour"][:, miss] == 0.0)
 
 
+def test_c0_ball_brackets_hold_one_crossing(orc):
+    """c = 0: d - eps falls monotonically through the eps-level sphere, so
+    every refinable hit's final bracket holds exactly one crossing and the
+    refined depth lies inside it."""
+    jb = _ball_job()
+    out = orc.render(jb)
+    hit = np.nonzero(((out["status"] & 7) == orc.STATUS_HIT) & ((out["status"] & orc.FLAG_UNREFINED) == 0))[0]
+    assert hit.size > 1000
+    lt, t, cr = orc.bracket_crossings(jb, hit)
+    assert np.all(cr == 1)
+    assert np.all((lt <= out["depth"][hit]) & (out["depth"][hit] <= t))
+
+
 def test_c0_ball_relative_eps_depth(orc):
     """eps = eps_rel * t: the refined depth solves 0.5 r(t) ln r(t) = eps_rel t."""
     jb = _ball_job(width=48, height=48, eps_abs=0.0, eps_rel=5e-4)
