@@ -45,7 +45,8 @@ STAGES = ("primary_march", "normals", "shadow_march")
 
 # sources of the forward kernels; the recorded HBM traffic is used only while
 # they are unchanged since the counters were taken
-KERNEL_SOURCES = ("frt_trace.hip", "frt_fractal.hpp", "frt_math.hpp", "frt_ray.hpp", "frt_job.hpp")
+KERNEL_SOURCES = ("frt_trace.hip", "frt_fractal.hpp", "frt_math.hpp", "frt_ray.hpp", "frt_job.hpp", "frt_normal.hpp",
+                  "frt_gradient.hpp")
 
 
 def kernel_sources_sha256():
