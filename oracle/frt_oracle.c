@@ -625,17 +625,20 @@ typedef struct {
     int entry_plane;
 } pixel_result;
 
-static void render_pixel(const or_camera* cam, const or_fractal* f, const or_plane* planes, int32_t n_planes,
-                         const or_march* mc, int32_t i, int32_t j, pixel_result* px) {
+/* Primary part of one ray (R6-R10): interval, march, refinement and normal,
+ * no shading.  px->depth is t* (-1 on a miss), px->normal the normal,
+ * px->status the class with the JUMP / UNREFINED flags; *lt receives the
+ * last-but-one march sample (-1 without one).                              */
+static void trace_primary(const or_fractal* f, const or_plane* planes, int32_t n_planes, const or_march* mc,
+                          const double o[3], const double dir[3], pixel_result* px, double* lt) {
     memset(px, 0, sizeof(*px));
-    double o[3], dir[3];
-    oracle_camera_ray(cam, i, j, o, dir);
     trace_result tr;
     trace_ray(f, planes, n_planes, o, dir, mc->eps_abs, mc->eps_rel, mc->eps_abs,
               mc->max_steps, mc->step_clamp, mc->t_max, &tr);
     px->steps = tr.steps; px->hit_iters = tr.hit_iters;
     px->de_evals = tr.de_evals; px->orbit_bodies = tr.orbit_bodies;
     px->raw_t = tr.t; px->entry_plane = tr.entry_plane;
+    *lt = tr.has_prev ? tr.lt : -1.0;
     if (tr.status == ST_MISS_BOUNDS || tr.status == ST_MISS_TMAX) {
         px->status = tr.status;
         px->depth = -1.0;
@@ -662,6 +665,19 @@ static void render_pixel(const or_camera* cam, const or_fractal* f, const or_pla
         estimate_normal(f, p, mc->eps_abs + mc->eps_rel * ts, mc->normal_mode, dir, nrm,
                         &px->de_evals, &px->orbit_bodies);
     }
+    px->depth = ts;
+    for (int k = 0; k < 3; ++k) px->normal[k] = nrm[k];
+    px->status = tr.status | flags;
+}
+
+static void render_pixel(const or_camera* cam, const or_fractal* f, const or_plane* planes, int32_t n_planes,
+                         const or_march* mc, int32_t i, int32_t j, pixel_result* px) {
+    double o[3], dir[3], lt;
+    oracle_camera_ray(cam, i, j, o, dir);
+    trace_primary(f, planes, n_planes, mc, o, dir, px, &lt);
+    if ((px->status & 7) < ST_HIT) return;            /* miss: normal and colour stay 0 */
+    double ts = px->depth;
+    const double* nrm = px->normal;
     double eps_s = mc->eps_abs + mc->eps_rel * ts;
     double L[3] = { mc->light[0], mc->light[1], mc->light[2] };
     normalize3(L);
@@ -673,12 +689,79 @@ static void render_pixel(const or_camera* cam, const or_fractal* f, const or_pla
         trace_result sh;
         trace_ray(f, planes, n_planes, q, L, eps_s, 0.0, eps_s, mc->max_steps, mc->step_clamp, mc->t_max, &sh);
         px->de_evals += sh.de_evals; px->orbit_bodies += sh.orbit_bodies;
-        if (sh.status >= ST_HIT) { vis = 0.0; flags |= ST_FLAG_SHADOWED; }
+        if (sh.status >= ST_HIT) { vis = 0.0; px->status |= ST_FLAG_SHADOWED; }
     }
     double lam = mc->k_ambient + mc->k_diffuse * fmax(0.0, ndl) * vis;
-    px->depth = ts;
-    for (int k = 0; k < 3; ++k) { px->normal[k] = nrm[k]; px->colour[k] = mc->albedo[k] * lam; }
-    px->status = tr.status | flags;
+    for (int k = 0; k < 3; ++k) px->colour[k] = mc->albedo[k] * lam;
+}
+
+/* Sign changes of g(s) = d(o + s dir) - eps(s) over `samples` + 1 uniform
+ * points of [lo, hi].                                                       */
+static int32_t count_crossings(const or_fractal* f, const or_march* mc, const double o[3], const double dir[3],
+                               double lo, double hi, int32_t samples) {
+    int count = 0, prev_sign = 0;
+    for (int32_t k = 0; k <= samples; ++k) {
+        double s = lo + (hi - lo) * (double)k / (double)samples;
+        double pt[3] = { o[0] + s * dir[0], o[1] + s * dir[1], o[2] + s * dir[2] };
+        double g = fractal_de(f, pt).d - (mc->eps_abs + mc->eps_rel * s);
+        int sg = g < 0.0 ? -1 : 1;
+        if (k > 0 && sg != prev_sign) ++count;
+        prev_sign = sg;
+    }
+    return count;
+}
+
+/* Primary part (trace_primary) of n explicit rays, origins and unit
+ * directions [n][3], in the fractal's own frame and units: the building
+ * block of scenes, whose objects the caller places by similarity maps.
+ * normal is [n][3]; lt the last-but-one sample; crossings (when samples > 0)
+ * the sign changes of d - eps over the final bracket of refinable hits.    */
+int oracle_trace_rays(const or_fractal* f, const or_plane* planes, int32_t n_planes, const or_march* mc,
+                      const double* orig, const double* dirs, int64_t n, int32_t samples, uint8_t* status,
+                      double* depth, double* normal, int32_t* steps, int32_t* hit_iters, double* raw_t, double* lt,
+                      int32_t* crossings, int64_t* de_evals, int64_t* orbit_bodies) {
+    if (!f || !mc || !orig || !dirs) return -1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t q = 0; q < n; ++q) {
+        pixel_result px;
+        double l;
+        trace_primary(f, planes, n_planes, mc, orig + 3 * q, dirs + 3 * q, &px, &l);
+        if (status) status[q] = (uint8_t)px.status;
+        if (depth) depth[q] = px.depth;
+        if (normal) for (int k = 0; k < 3; ++k) normal[3 * q + k] = px.normal[k];
+        if (steps) steps[q] = px.steps;
+        if (hit_iters) hit_iters[q] = px.hit_iters;
+        if (raw_t) raw_t[q] = px.raw_t;
+        if (lt) lt[q] = l;
+        if (crossings) {
+            crossings[q] = ((px.status & 7) == ST_HIT && l >= 0.0 && samples > 0)
+                               ? count_crossings(f, mc, orig + 3 * q, dirs + 3 * q, l, px.raw_t, samples)
+                               : 0;
+        }
+        if (de_evals) de_evals[q] = px.de_evals;
+        if (orbit_bodies) orbit_bodies[q] = px.orbit_bodies;
+    }
+    return 0;
+}
+
+/* Shadow test of n explicit rays (R11): does the ray from q [n][3] along the
+ * unit direction light [n][3] hit the object (threshold eps[n], started at
+ * eps, the march's step cap and range)?  hit[n] is 1 or 0.                  */
+int oracle_occluded(const or_fractal* f, const or_plane* planes, int32_t n_planes, const or_march* mc,
+                    const double* q, const double* light, const double* eps, int64_t n, uint8_t* hit) {
+    if (!f || !mc || !q || !light || !eps || !hit) return -1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t k = 0; k < n; ++k) {
+        trace_result sh;
+        trace_ray(f, planes, n_planes, q + 3 * k, light + 3 * k, eps[k], 0.0, eps[k], mc->max_steps,
+                  mc->step_clamp, mc->t_max, &sh);
+        hit[k] = sh.status >= ST_HIT ? 1 : 0;
+    }
+    return 0;
 }
 
 /* Render the listed pixels (linear index j*W + i), or all when pix == NULL.
@@ -746,16 +829,7 @@ int oracle_bracket_crossings(const or_camera* cam, const or_fractal* f, const or
         if (tr.status != ST_HIT || !tr.has_prev) continue;
         lt[q] = tr.lt;
         t[q] = tr.t;
-        int count = 0, prev_sign = 0;
-        for (int32_t k = 0; k <= samples; ++k) {
-            double s = tr.lt + (tr.t - tr.lt) * (double)k / (double)samples;
-            double pt[3] = { o[0] + s * dir[0], o[1] + s * dir[1], o[2] + s * dir[2] };
-            double g = fractal_de(f, pt).d - (mc->eps_abs + mc->eps_rel * s);
-            int sg = g < 0.0 ? -1 : 1;
-            if (k > 0 && sg != prev_sign) ++count;
-            prev_sign = sg;
-        }
-        crossings[q] = count;
+        crossings[q] = count_crossings(f, mc, o, dir, tr.lt, tr.t, samples);
     }
     return 0;
 }

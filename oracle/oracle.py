@@ -90,6 +90,14 @@ def lib():
                                             dp, P(ctypes.c_int32)]
         L.oracle_pixel_jacobian.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int32
+        L.oracle_trace_rays.argtypes = [P(Fractal), P(Plane), ctypes.c_int32, P(March), dp, dp, ctypes.c_int64,
+                                        ctypes.c_int32, P(ctypes.c_uint8), dp, dp, P(ctypes.c_int32),
+                                        P(ctypes.c_int32), dp, dp, P(ctypes.c_int32), P(ctypes.c_int64),
+                                        P(ctypes.c_int64)]
+        L.oracle_trace_rays.restype = ctypes.c_int
+        L.oracle_occluded.argtypes = [P(Fractal), P(Plane), ctypes.c_int32, P(March), dp, dp, dp, ctypes.c_int64,
+                                      P(ctypes.c_uint8)]
+        L.oracle_occluded.restype = ctypes.c_int
         L.oracle_bracket_crossings.argtypes = [P(Camera), P(Fractal), P(Plane), ctypes.c_int32, P(March),
                                                P(ctypes.c_int64), ctypes.c_int64, ctypes.c_int32, dp, dp,
                                                P(ctypes.c_int32)]
@@ -338,4 +346,133 @@ def normal_perturbed(fractal, points, dirs, eps, mode, rel, seed):
     L.oracle_normal_perturbed(ctypes.byref(fr), _ptr(pts, ctypes.c_double), _ptr(drs, ctypes.c_double),
                               _ptr(ep, ctypes.c_double), pts.shape[0], m, float(rel), int(seed),
                               _ptr(out, ctypes.c_double))
+    return out
+
+
+# ---------------------------------------------------------------- scenes
+def trace_rays(fractal, planes, march, origins, dirs, samples=0):
+    """Primary part (march, refinement, normal; no shading) of explicit rays
+    in the fractal's own frame and units.  Returns status, depth, normal
+    [n, 3], steps, hit_iters, raw_t, lt (last-but-one sample), crossings
+    (sign changes of d - eps over the final bracket, if samples > 0)."""
+    L = lib()
+    fr, mc = make_fractal(fractal), make_march(march)
+    pl, npl = make_planes(planes)
+    o = np.ascontiguousarray(origins, dtype=np.float64).reshape(-1, 3)
+    d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    n = o.shape[0]
+    out = {"status": np.empty(n, np.uint8), "depth": np.empty(n), "normal": np.empty((n, 3)),
+           "steps": np.empty(n, np.int32), "hit_iters": np.empty(n, np.int32), "raw_t": np.empty(n),
+           "lt": np.empty(n), "crossings": np.zeros(n, np.int32), "de_evals": np.empty(n, np.int64),
+           "orbit_bodies": np.empty(n, np.int64)}
+    rc = L.oracle_trace_rays(ctypes.byref(fr), pl, npl, ctypes.byref(mc), _ptr(o, ctypes.c_double),
+                             _ptr(d, ctypes.c_double), n, int(samples), _ptr(out["status"], ctypes.c_uint8),
+                             _ptr(out["depth"], ctypes.c_double), _ptr(out["normal"], ctypes.c_double),
+                             _ptr(out["steps"], ctypes.c_int32), _ptr(out["hit_iters"], ctypes.c_int32),
+                             _ptr(out["raw_t"], ctypes.c_double), _ptr(out["lt"], ctypes.c_double),
+                             _ptr(out["crossings"], ctypes.c_int32), _ptr(out["de_evals"], ctypes.c_int64),
+                             _ptr(out["orbit_bodies"], ctypes.c_int64))
+    if rc != 0:
+        raise RuntimeError("oracle_trace_rays failed")
+    return out
+
+
+def occluded(fractal, planes, march, q, light, eps):
+    """Shadow test of explicit rays in the fractal's frame: bool [n]."""
+    L = lib()
+    fr, mc = make_fractal(fractal), make_march(march)
+    pl, npl = make_planes(planes)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+    lt = np.ascontiguousarray(light, dtype=np.float64).reshape(-1, 3)
+    ep = np.ascontiguousarray(eps, dtype=np.float64).reshape(-1)
+    hit = np.zeros(q.shape[0], np.uint8)
+    rc = L.oracle_occluded(ctypes.byref(fr), pl, npl, ctypes.byref(mc), _ptr(q, ctypes.c_double),
+                           _ptr(lt, ctypes.c_double), _ptr(ep, ctypes.c_double), q.shape[0],
+                           _ptr(hit, ctypes.c_uint8))
+    if rc != 0:
+        raise RuntimeError("oracle_occluded failed")
+    return hit.astype(bool)
+
+
+def object_frame(ob):
+    """(R, T, s) of a scene object: x_obj = R^T (x - T) / s."""
+    R = np.array(ob.get("rotation") or (1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0), dtype=np.float64).reshape(3, 3)
+    T = np.array(ob.get("translation", (0.0, 0.0, 0.0)), dtype=np.float64)
+    return R, T, float(ob.get("scale", 1.0))
+
+
+def object_march(march, s):
+    """The march settings in an object's units: eps_abs, step_clamp and
+    t_max divided by its scale (eps_rel and the rest unchanged)."""
+    m = dict(march)
+    m["eps_abs"] = float(march["eps_abs"]) / s
+    m["step_clamp"] = float(march["step_clamp"]) / s
+    m["t_max"] = float(march["t_max"]) / s
+    return m
+
+
+def render_scene(scene, pixels=None, samples=0):
+    """A scene of several fractal objects (Sec. 3): every primary ray is
+    traced through each object in its own frame and the closest hit kept
+    (ties to the lower index); the hit is shaded in world space and its
+    shadow ray is blocked by a hit on any object.  Returns the render() dict
+    plus object_id (-1 on a miss), lt and crossings of the object hit."""
+    cam, mc = scene["camera"], scene["march"]
+    W, H = int(cam["width"]), int(cam["height"])
+    pix = np.arange(W * H) if pixels is None else np.asarray(pixels, np.int64)
+    o, d = camera_rays(cam, pix)
+    n = pix.size
+    best = np.full(n, -1, np.int64)
+    best_t = np.full(n, np.inf)
+    entered = np.zeros(n, bool)
+    status = np.zeros(n, np.uint8)
+    nrm = np.zeros((n, 3))
+    keep = {k: np.zeros(n, dt) for k, dt in (("steps", np.int32), ("hit_iters", np.int32), ("raw_t", np.float64),
+                                               ("lt", np.float64), ("crossings", np.int32),
+                                               ("de_evals", np.int64), ("orbit_bodies", np.int64))}
+    for k, ob in enumerate(scene["objects"]):
+        R, T, s = object_frame(ob)
+        r = trace_rays(ob["fractal"], ob.get("planes", []), object_march(mc, s), (o - T) @ R / s, d @ R, samples)
+        cls = r["status"] & 7
+        entered |= cls != STATUS_MISS_BOUNDS
+        tw = r["depth"] * s
+        better = (cls >= STATUS_HIT) & (tw < best_t)
+        best[better] = k
+        best_t[better] = tw[better]
+        status[better] = r["status"][better]
+        nrm[better] = r["normal"][better] @ R.T
+        for key in ("steps", "hit_iters", "crossings", "de_evals", "orbit_bodies"):
+            keep[key][better] = r[key][better]
+        keep["raw_t"][better] = r["raw_t"][better] * s
+        keep["lt"][better] = np.where(r["lt"][better] >= 0.0, r["lt"][better] * s, -1.0)
+    hit = best >= 0
+    nl = np.linalg.norm(nrm, axis=1, keepdims=True)
+    nrm = np.where(nl > 0, nrm / np.where(nl > 0, nl, 1.0), nrm)
+    status[~hit] = np.where(entered[~hit], STATUS_MISS_TMAX, STATUS_MISS_BOUNDS)
+    depth = np.where(hit, best_t, -1.0)
+    Ld = np.array(mc["light_dir"], dtype=np.float64)
+    Ld /= np.linalg.norm(Ld)
+    ndl = nrm @ Ld
+    vis = np.ones(n)
+    if mc["shadow"]:
+        lit = np.nonzero(hit & (ndl > 0.0))[0]
+        eps_s = mc["eps_abs"] + mc["eps_rel"] * depth[lit]
+        q = o[lit] + depth[lit, None] * d[lit] + 4.0 * eps_s[:, None] * nrm[lit]
+        shadowed = np.zeros(lit.size, bool)
+        for ob in scene["objects"]:
+            R, T, s = object_frame(ob)
+            todo = ~shadowed
+            if not todo.any():
+                break
+            idx = np.nonzero(todo)[0]
+            hit_k = occluded(ob["fractal"], ob.get("planes", []), object_march(mc, s), (q[idx] - T) @ R / s,
+                             np.broadcast_to(Ld @ R, (idx.size, 3)), eps_s[idx] / s)
+            shadowed[idx[hit_k]] = True
+        vis[lit[shadowed]] = 0.0
+        status[lit[shadowed]] |= FLAG_SHADOWED
+    lam = mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0.0, ndl) * vis
+    colour = np.where(hit[None, :], np.array(mc["albedo"], dtype=np.float64)[:, None] * lam[None, :], 0.0)
+    out = {"depth": depth, "normal": np.where(hit[None, :], nrm.T, 0.0), "colour": colour, "status": status,
+           "object_id": best}
+    out.update(keep)
     return out

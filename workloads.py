@@ -206,6 +206,65 @@ def with_size(jb, width, height):
     return out
 
 
+# ---------------------------------------------------------------------------
+# Iteration-count animation (Fig. 2 animates the n = 8 Mandelbulb by the
+# number of orbit iterations): frame k of n_frames uses max_iter = k + 1,
+# everything else as one Mandelbulb view (azimuth 0.7, elevation 0.25).
+# ---------------------------------------------------------------------------
+def iteration_animation(n_frames=10, width=480, height=270, shadow=True):
+    return [bulb_view(0.7, 0.25, width=width, height=height, max_iter=k + 1, shadow=shadow)
+            for k in range(n_frames)]
+
+
+# ---------------------------------------------------------------------------
+# Scenes of several procedural objects (Sec. 3, Fig. 4), each placed by a
+# rotation R (object to world), a translation T and a uniform scale s.
+# ---------------------------------------------------------------------------
+def rotation(axis, angle):
+    """Rotation by `angle` radians about a unit `axis`, row-major, float32."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+    R = np.eye(3) + math.sin(angle) * K + (1.0 - math.cos(angle)) * (K @ K)
+    return f32v(R.ravel())
+
+
+def scene_object(fractal, planes=(), rot=None, translation=(0.0, 0.0, 0.0), scale=1.0):
+    return {"fractal": fractal, "planes": [dict(p) for p in planes],
+            "rotation": list(rot) if rot is not None else f32v(np.eye(3).ravel()),
+            "translation": f32v(translation), "scale": f32(scale)}
+
+
+def scene(cam, objects, mc):
+    return {"camera": cam, "objects": objects, "march": mc}
+
+
+# Julia (the Julia view's c, cut plane) and n = 8 Mandelbulb side by side,
+# each rotated and scaled, eye (0, 1, 4.5), 45 deg, eps = 5e-4 t, central
+# normals, shadow rays.
+def julia_bulb_scene(width=320, height=200, shadow=True, normal_mode="central", max_steps=512):
+    objs = [scene_object(julia(JULIA_C1, 11), planes=[plane([0.3, 0.2, 1.0], 0.05)],
+                         rot=rotation([0.0, 1.0, 0.0], 0.6), translation=(-1.35, 0.0, 0.0), scale=0.9),
+            scene_object(bulb(8.0, 10), rot=rotation([1.0, 0.0, 0.2], 0.4), translation=(1.3, 0.1, -0.3),
+                         scale=1.1)]
+    return scene(camera((0.0, 1.0, 4.5), width, height),
+                 objs, march(max_steps, eps_rel=5e-4, normal_mode=normal_mode, shadow=shadow, t_max=20.0))
+
+
+# Three objects that overlap on screen and in depth and shadow one another:
+# a small cubic Julia in front, a real-power (n = 6.37) Mandelbulb behind it
+# and a large degree-2 Julia further back, lit from the upper front.
+def overlap_scene(width=256, height=192, shadow=True, normal_mode="tetra", max_steps=512):
+    objs = [scene_object(julia(JULIA_C3, 9, degree=3), rot=rotation([0.3, 1.0, 0.0], 1.1),
+                         translation=(0.35, 0.3, 1.2), scale=0.45),
+            scene_object(bulb(6.37, 10), rot=rotation([0.0, 0.0, 1.0], 0.3), translation=(-0.2, 0.0, 0.0),
+                         scale=0.9),
+            scene_object(julia([-0.5, 0.3, 0.1, 0.0], 11), planes=[plane([0.0, 0.0, 1.0], 0.2)],
+                         rot=rotation([1.0, 0.0, 0.0], -0.5), translation=(0.3, -0.4, -2.0), scale=1.6)]
+    return scene(camera((0.0, 0.4, 4.0), width, height),
+                 objs, march(max_steps, eps_rel=5e-4, normal_mode=normal_mode, shadow=shadow, t_max=20.0))
+
+
 def stratified_pixels(width, height, stride, seed=0):
     """One pixel per stride x stride cell (seeded position inside the cell)."""
     rng = np.random.default_rng(seed)
