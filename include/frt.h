@@ -222,6 +222,47 @@ frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float*
                                float* const* grad_pixel, float* grad_c, float* grad_power, float* grad_plane,
                                void* workspace, size_t ws_bytes, void* stream);
 
+/* One object of a scene (Sec. 3: every procedural object sits in its own
+ * box with a transform from world space to its local space).  The map from
+ * world to object space is the similarity x_obj = R^T (x - T) / s with
+ * R = rotation (object-to-world, row-major, a proper rotation: R R^T = I to
+ * 1e-4 and det R > 0), T = translation and s = scale > 0.  Distances scale
+ * by s, so the estimate stays a distance bound (a general affine map would
+ * not keep it one).  frac and planes are in object space; the fractal's
+ * bounding sphere plays the role of the paper's box.                       */
+typedef struct {
+    frt_fractal frac;
+    frt_plane planes[2];
+    int32_t n_planes;           /* [0, 2]                                    */
+    float rotation[9];
+    float translation[3];
+    float scale;
+} frt_object;
+
+/* Device workspace of frt_render_scene over n_objects objects (a 1 KiB
+ * header and the object table), 256-byte aligned.                          */
+size_t frt_scene_workspace_bytes(int32_t n_objects);
+
+/* Render one view of a scene of n_objects (1..16) objects in one launch.
+ * Every primary ray is marched through each object in its own frame (the
+ * world ray mapped by the object's similarity, with eps_abs, step_clamp and
+ * t_max divided by its scale and eps_rel unchanged, so eps(t) stays a world
+ * quantity) and the closest hit is kept, ties going to the lower index (the
+ * closest-hit rule of the paper's intersection shaders).  The hit's normal
+ * is computed in object space and mapped to world space by R; shading is
+ * done in world space and the shadow ray of a lit hit is blocked by a hit
+ * on any object.  march and out as in frt_render (depth in world units).
+ * Counter planes 0-3 describe the primary march of the object hit (zero on
+ * a miss), 4-5 its normal, 6-7 the shadow ray over all objects.  A miss is
+ * a t_max miss when the ray entered any object's interval, else a bounds
+ * miss.  object_id: int32[H*W] (device, may be NULL) receives the index of
+ * the object hit, -1 on a miss.
+ * Errors: FRT_EINVAL (nothing launched) for invalid parameters, naming the
+ * object; FRT_ENOMEM for a small workspace; FRT_EHIP for a failed launch. */
+frt_status frt_render_scene(const frt_camera* cam, const frt_object* objects, int32_t n_objects,
+                            const frt_march* march, frt_frame out, int32_t* object_id, void* workspace,
+                            size_t ws_bytes, void* stream);
+
 /* Distance estimate (Sec. 2, Eq. 2-4) at n points, the same orbit code the
  * renderer marches with: points float[n][3] (device), d float[n] (device),
  * iters int32[n] (device, may be NULL) receives the escape count (max_iter:

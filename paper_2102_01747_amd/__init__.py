@@ -57,6 +57,11 @@ class Frame(ctypes.Structure):
                 ("status", ctypes.c_void_p), ("counters", ctypes.c_void_p)]
 
 
+class Object(ctypes.Structure):
+    _fields_ = [("frac", Fractal), ("planes", Plane * 2), ("n_planes", ctypes.c_int32),
+                ("rotation", ctypes.c_float * 9), ("translation", f3), ("scale", ctypes.c_float)]
+
+
 class Job(ctypes.Structure):
     _fields_ = [("cam", Camera), ("frac", Fractal), ("planes", Plane * 2), ("n_planes", ctypes.c_int32),
                 ("march", March), ("out", Frame)]
@@ -91,6 +96,10 @@ def lib():
         L.frt_distance.argtypes = [P(Fractal), vp, ctypes.c_int64, vp, vp, vp]
         L.frt_distance.restype = ctypes.c_int
         L.frt_normal_at.argtypes = [P(Fractal), i32, vp, vp, ctypes.c_int64, vp, vp]
+        L.frt_scene_workspace_bytes.argtypes = [i32]
+        L.frt_scene_workspace_bytes.restype = ctypes.c_size_t
+        L.frt_render_scene.argtypes = [P(Camera), P(Object), i32, P(March), Frame, vp, vp, ctypes.c_size_t, vp]
+        L.frt_render_scene.restype = ctypes.c_int
         L.frt_normal_at.restype = ctypes.c_int
         L.frt_math_eval.argtypes = [i32, vp, vp, vp, ctypes.c_int64, vp]
         L.frt_math_eval.restype = ctypes.c_int
@@ -210,7 +219,36 @@ def make_job(job, frame):
                make_frame(frame))
 
 
+def make_object(ob):
+    pl, npl = make_planes(ob.get("planes", []))
+    rot = [float(x) for x in (ob.get("rotation") or (1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0))]
+    return Object(make_fractal(ob["fractal"]), pl, npl, (ctypes.c_float * 9)(*rot),
+                  f3(*ob.get("translation", (0.0, 0.0, 0.0))), float(ob.get("scale", 1.0)))
+
+
 # ------------------------------------------------------------------- render
+def render_scene(scene, device="cuda", counters=False, out=None, workspace=None):
+    """Render a scene (camera, list of objects, march) in one launch; returns
+    the frame dict with an extra "object_id" plane (int32, -1 on a miss)."""
+    L = lib()
+    dev = _device(device)
+    objs = scene["objects"]
+    fr = out if out is not None else alloc_frame(scene, dev, counters)
+    if "object_id" not in fr:
+        fr["object_id"] = torch.empty(fr["depth"].numel(), device=dev, dtype=torch.int32)
+    n = len(objs)
+    arr = (Object * max(n, 1))(*[make_object(o) for o in objs])
+    nbytes = int(L.frt_scene_workspace_bytes(max(n, 1)))
+    if workspace is None:
+        ws = torch.empty(nbytes + 256, device=dev, dtype=torch.uint8)
+        off = (-ws.data_ptr()) % 256
+        workspace = ws[off:off + nbytes]
+    cam, mc = make_camera(scene["camera"]), make_march(scene["march"])
+    _check(L.frt_render_scene(ctypes.byref(cam), arr, n, ctypes.byref(mc), make_frame(fr), _ptr(fr["object_id"]),
+                              _ptr(workspace), workspace.numel(), _stream(dev)))
+    return fr
+
+
 def render(job, device="cuda", counters=False, out=None, workspace=None):
     """Render one job asynchronously on the current stream; returns the
     frame dict (depth, normal, colour, status[, counters])."""

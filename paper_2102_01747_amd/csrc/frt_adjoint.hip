@@ -73,7 +73,6 @@ __device__ __forceinline__ void julia_de_tan(const OrbitParams& P, double x, dou
     ta[NP] = vx; tb[NP] = vy; te[NP] = vz; tw[NP] = 0.0; L[NP] = 0.0;
     double m2 = fma(a, a, fma(b, b, e * e));
     double prod = 1.0;
-    int bodies = 0;
     for (int i = 0; i < P.max_iter; ++i) {
         const double im2 = m2 > 0.0 ? 1.0 / m2 : 0.0;
         const double vv = fma(b, b, fma(e, e, w * w));
@@ -115,7 +114,6 @@ __device__ __forceinline__ void julia_de_tan(const OrbitParams& P, double x, dou
         e = fma(Q, e, c2);
         w = fma(Q, w, c3);
         m2 = fma(a, a, fma(b, b, fma(e, e, w * w)));
-        ++bodies;
         if (m2 > P.bail2) break;
     }
     if (!(m2 > 0.0)) {

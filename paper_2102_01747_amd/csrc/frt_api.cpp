@@ -355,12 +355,12 @@ std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;
 hipStream_t g_capture_stream = nullptr;
 
-// Copy header + job table (+ the adjoint's table, if given) into the
-// workspace through one pinned staging buffer.
-frt_status upload_table(const std::vector<JobDev>& jobs, const WorkspaceHeader& hdr, void* workspace,
-                        hipStream_t stream, const std::vector<frt::AdjointJob>* ajobs = nullptr) {
-    const size_t table = sizeof(WorkspaceHeader) + jobs.size() * sizeof(JobDev);
-    const size_t bytes = table + (ajobs ? ajobs->size() * sizeof(frt::AdjointJob) : 0);
+// Copy consecutive host blocks into the start of the workspace through one
+// pinned staging buffer (reused; a new upload waits for the previous copy).
+frt_status upload_parts(const void* const* parts, const size_t* sizes, int n_parts, void* workspace,
+                        hipStream_t stream) {
+    size_t bytes = 0;
+    for (int i = 0; i < n_parts; ++i) bytes += sizes[i];
     std::lock_guard<std::mutex> lk(g_stage_mu);
     hipError_t e;
     if (g_stage.pending) {
@@ -380,15 +380,26 @@ frt_status upload_table(const std::vector<JobDev>& jobs, const WorkspaceHeader& 
         e = hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     }
-    std::memcpy(g_stage.host, &hdr, sizeof(hdr));
-    std::memcpy(static_cast<char*>(g_stage.host) + sizeof(hdr), jobs.data(), jobs.size() * sizeof(JobDev));
-    if (ajobs) std::memcpy(static_cast<char*>(g_stage.host) + table, ajobs->data(), bytes - table);
+    size_t off = 0;
+    for (int i = 0; i < n_parts; ++i) {
+        if (sizes[i]) std::memcpy(static_cast<char*>(g_stage.host) + off, parts[i], sizes[i]);
+        off += sizes[i];
+    }
     e = hipMemcpyAsync(workspace, g_stage.host, bytes, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
     e = hipEventRecord(g_stage.done, stream);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     g_stage.pending = true;
     return FRT_OK;
+}
+
+// Header + job table (+ the adjoint's table, if given).
+frt_status upload_table(const std::vector<JobDev>& jobs, const WorkspaceHeader& hdr, void* workspace,
+                        hipStream_t stream, const std::vector<frt::AdjointJob>* ajobs = nullptr) {
+    const void* parts[3] = {&hdr, jobs.data(), ajobs ? static_cast<const void*>(ajobs->data()) : nullptr};
+    const size_t sizes[3] = {sizeof(hdr), jobs.size() * sizeof(JobDev),
+                             ajobs ? ajobs->size() * sizeof(frt::AdjointJob) : 0};
+    return upload_parts(parts, sizes, 3, workspace, stream);
 }
 
 frt_status check_workspace(void* workspace, size_t ws_bytes, int32_t n_jobs) {
@@ -407,6 +418,77 @@ size_t frt_workspace_bytes(int32_t n_jobs) {
     if (n_jobs < 1) n_jobs = 1;
     const int64_t per_job = int64_t(sizeof(JobDev)) + int64_t(sizeof(frt::AdjointJob));
     return size_t(round_up(int64_t(sizeof(WorkspaceHeader)) + int64_t(n_jobs) * per_job, 256));
+}
+
+size_t frt_scene_workspace_bytes(int32_t n_objects) {
+    if (n_objects < 1) n_objects = 1;
+    return size_t(round_up(int64_t(sizeof(WorkspaceHeader)) + int64_t(n_objects) * int64_t(sizeof(frt::SceneObject)),
+                           256));
+}
+
+frt_status frt_render_scene(const frt_camera* cam, const frt_object* objects, int32_t n_objects,
+                            const frt_march* march, frt_frame out, int32_t* object_id, void* workspace,
+                            size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    if (!objects || n_objects < 1 || n_objects > frt::kMaxSceneObjects)
+        return fail(FRT_EINVAL, "n_objects must be in [1, 16] with a non-null table");
+    std::string why;
+    const frt_object& o0 = objects[0];
+    if (!validate(cam, &o0.frac, o0.planes, o0.n_planes, march, &out, true, why)) return fail(FRT_EINVAL, why);
+    if (!workspace) return fail(FRT_EINVAL, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FRT_EINVAL, "workspace not 256-byte aligned");
+    if (ws_bytes < frt_scene_workspace_bytes(n_objects)) return fail(FRT_ENOMEM, "workspace too small");
+    std::vector<frt::SceneObject> table(static_cast<size_t>(n_objects));
+    for (int k = 0; k < n_objects; ++k) {
+        const frt_object& ob = objects[k];
+        const std::string tag = "object " + std::to_string(k) + ": ";
+        if (!finite_n(ob.rotation, 9) || !finite_n(ob.translation, 3) || !finite(ob.scale))
+            return fail(FRT_EINVAL, tag + "non-finite transform");
+        if (!(ob.scale > 0.0f)) return fail(FRT_EINVAL, tag + "scale must be > 0");
+        // R must be a rotation: R R^T = I (to float accuracy) and det R = +1
+        const float* R = ob.rotation;
+        double worst = 0.0;
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double d = 0.0;
+                for (int i = 0; i < 3; ++i) d += double(R[3 * r + i]) * R[3 * c + i];
+                worst = std::max(worst, std::fabs(d - (r == c ? 1.0 : 0.0)));
+            }
+        const double det = double(R[0]) * (double(R[4]) * R[8] - double(R[5]) * R[7]) -
+                           double(R[1]) * (double(R[3]) * R[8] - double(R[5]) * R[6]) +
+                           double(R[2]) * (double(R[3]) * R[7] - double(R[4]) * R[6]);
+        if (!(worst <= 1e-4 && det > 0.0)) return fail(FRT_EINVAL, tag + "rotation is not a proper rotation");
+        const double sc = ob.scale;
+        frt_march mo = *march;
+        mo.eps_abs = float(double(march->eps_abs) / sc);
+        mo.step_clamp = float(double(march->step_clamp) / sc);
+        mo.t_max = float(double(march->t_max) / sc);
+        if (!validate(cam, &ob.frac, ob.planes, ob.n_planes, &mo, nullptr, false, why))
+            return fail(FRT_EINVAL, tag + why);
+        frt::SceneObject& S = table[size_t(k)];
+        std::memset(&S, 0, sizeof(S));
+        frt_frame none{};
+        pack(cam, &ob.frac, ob.planes, ob.n_planes, &mo, none, 0, S.job);
+        for (int i = 0; i < 9; ++i) S.rot[i] = R[i];
+        for (int i = 0; i < 3; ++i) S.trans[i] = ob.translation[i];
+        S.scale = ob.scale;
+        S.inv_scale = float(1.0 / sc);
+        S.variant = variant_of(S.job);
+    }
+    JobDev camJ;
+    pack(cam, &o0.frac, o0.planes, o0.n_planes, march, out, 0, camJ);
+    WorkspaceHeader hdr;
+    std::memset(&hdr, 0, sizeof(hdr));
+    hdr.n_jobs = n_objects;
+    const void* parts[2] = {&hdr, table.data()};
+    const size_t sizes[2] = {sizeof(hdr), table.size() * sizeof(frt::SceneObject)};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    frt_status s = upload_parts(parts, sizes, 2, workspace, st);
+    if (s != FRT_OK) return s;
+    const auto* objs = reinterpret_cast<const frt::SceneObject*>(static_cast<char*>(workspace) + sizeof(hdr));
+    hipError_t e = frt::launch_scene(objs, n_objects, camJ, object_id, st);
+    if (e != hipSuccess) return hip_fail(e, "scene launch");
+    return FRT_OK;
 }
 
 frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_plane* planes, int32_t n_planes,

@@ -43,6 +43,9 @@ hipError_t launch_distance(int variant, const OrbitParams& P, const float* pts, 
 // a zero or non-finite gradient).
 hipError_t launch_normal_query(int variant, const OrbitParams& P, int mode, const float* pts, const float* eps,
                                long long n, float* out, hipStream_t stream);
+// One view of a scene (frt_scene.hip): objs is the device table of n_obj
+// objects, cam the world camera, march and output planes.
+hipError_t launch_scene(const SceneObject* objs, int n_obj, const JobDev& cam, int* object_id, hipStream_t stream);
 hipError_t launch_math(int func, const float* x, const float* y, float* out, long long n, hipStream_t stream);
 
 // Adjoint over the hit pixels of a batch (frt_adjoint.hip): zeroes the

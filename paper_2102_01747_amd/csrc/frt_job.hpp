@@ -75,6 +75,19 @@ struct alignas(16) JobDev {
     double sx_d, sy_d;
 };
 
+// One object of a scene: its fractal, planes and march settings in object
+// units (eps_abs, step_clamp and t_max divided by the scale), and the
+// similarity x_obj = R^T (x - T) / s from world space (rot row-major R).
+constexpr int kMaxSceneObjects = 16;
+struct alignas(16) SceneObject {
+    JobDev job;
+    float rot[9];
+    float trans[3];
+    float scale, inv_scale;
+    int32_t variant;
+    int32_t pad[3];
+};
+
 // Gradient slots per job: c0..c3, power, plane 0 (raw n xyz, d), plane 1.
 constexpr int kGradSlots = 13;
 

@@ -272,3 +272,114 @@ def assert_parity(stats, hit_agree=0.999, depth_ok=1.0, normal_ok=0.999, class_a
     assert stats["normal_ok"] >= normal_ok, msg
     assert stats["colour_ok"] >= normal_ok, msg
     assert stats["miss_encoding_ok"], msg
+
+
+# ----------------------------------------------------------------- scenes
+def id_neighbour_flags(id_img, status_img):
+    """Per pixel: does any 8-neighbour show another object (or a miss), or
+    differ in cut-face-ness?"""
+    cut = (status_img & CLS_MASK) == 3
+    H, W = id_img.shape
+    diff = np.zeros((H, W), bool)
+    ip = np.pad(id_img, 1, mode="edge")
+    cp = np.pad(cut, 1, mode="edge")
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dy == 0 and dx == 0:
+                continue
+            diff |= (ip[1 + dy:1 + dy + H, 1 + dx:1 + dx + W] != id_img)
+            diff |= (cp[1 + dy:1 + dy + H, 1 + dx:1 + dx + W] != cut)
+    return diff
+
+
+def compare_scene(orc, sc, g, o, neigh_diff):
+    """Scene parity (full image): object ids over every pixel; class, depth,
+    normal and colour as in compare() on the pixels where both sides hit
+    the same object and that lie outside B (with the object id in the
+    neighbour rule), the normal rule evaluated in the object's own frame at
+    the GPU's hit point and rotated back."""
+    cam, mc = sc["camera"], sc["march"]
+    n = o["depth"].size
+    gid = g["object_id"].astype(np.int64)
+    oid = o["object_id"].astype(np.int64)
+    gs, os_ = g["status"].astype(np.int64), o["status"].astype(np.int64)
+    gc, oc = gs & CLS_MASK, os_ & CLS_MASK
+    stats = {"pixels": int(n), "id_agree": float(np.mean(gid == oid)),
+             "hit_agree": float(np.mean((gid >= 0) == (oid >= 0))),
+             "gpu_hits": int((gid >= 0).sum()), "oracle_hits": int((oid >= 0).sum())}
+    orig, dirs = orc.camera_rays(cam, np.arange(n))
+    B = boundary_set(g, o, neigh_diff, dirs)
+    both = (gid == oid) & (gid >= 0) & ~B
+    stats["boundary_frac"] = float(B.mean())
+    stats["compared"] = int(both.sum())
+    stats["class_agree"] = float(np.mean(gc[both] == oc[both])) if both.any() else 1.0
+    idx = np.nonzero(both)[0]
+    gd = g["depth"][idx].astype(np.float64)
+    ts = o["depth"][idx]
+    eps = mc["eps_abs"] + mc["eps_rel"] * ts
+    derr = np.abs(gd - ts)
+    ok = derr <= 2 * eps
+    multi = np.zeros(ok.shape, bool)
+    for k, ob in enumerate(sc["objects"]):
+        sel = np.nonzero(~ok & (gid[idx] == k))[0]
+        if sel.size == 0:
+            continue
+        R, T, s = orc.object_frame(ob)
+        pi = idx[sel]
+        r = orc.trace_rays(ob["fractal"], ob.get("planes", []), orc.object_march(mc, s), (orig[pi] - T) @ R / s,
+                           dirs[pi] @ R, samples=256)
+        lt, tt = r["lt"] * s, r["raw_t"] * s
+        e2 = 2 * eps[sel]
+        valid = (r["crossings"] > 1) & (lt >= 0) & (gd[sel] >= lt - e2) & (gd[sel] <= tt + e2)
+        ok[sel[valid]] = True
+        multi[sel[valid]] = True
+    stats["depth_multi_root"] = int(multi.sum())
+    stats["depth_ok"] = float(np.mean(ok)) if idx.size else 1.0
+    stats["depth_err_max_over_eps"] = float(np.max(np.where(multi, 0.0, derr) / eps)) if idx.size else 0.0
+    # normals in each object's frame at the GPU's hit point
+    n_at = np.zeros((idx.size, 3))
+    ill = np.zeros(idx.size, bool)
+    cut = gc[idx] == 3
+    on = o["normal"].T
+    for k, ob in enumerate(sc["objects"]):
+        sel = np.nonzero((gid[idx] == k) & ~cut)[0]
+        if sel.size == 0:
+            continue
+        R, T, s = orc.object_frame(ob)
+        pi = idx[sel]
+        p_w = orig[pi] + gd[sel, None] * dirs[pi]
+        p_o = (p_w - T) @ R / s
+        d_o = dirs[pi] @ R
+        e_o = (mc["eps_abs"] + mc["eps_rel"] * gd[sel]) / s
+        n_at[sel] = orc.normal_at(ob["fractal"], p_o, d_o, e_o, mc["normal_mode"]) @ R.T
+        ill[sel] = normal_ill_conditioned(orc, ob["fractal"], mc, p_o, d_o, e_o)
+    n_at[cut] = on[idx][cut]
+    gn = g["normal"].T[idx]
+    ang = angle(gn, n_at) if idx.size else np.zeros(0)
+    wc = ~ill
+    stats["normal_boundary_frac"] = float(ill.mean()) if idx.size else 0.0
+    stats["normal_ok"] = float(np.mean(ang[wc] <= 1e-3)) if wc.any() else 1.0
+    stats["normal_ang_p99"] = float(np.percentile(ang[wc], 99)) if wc.any() else 0.0
+    stats["normal_ang_max"] = float(np.max(ang[wc])) if wc.any() else 0.0
+    keep = np.zeros(n, bool)
+    keep[idx[wc]] = True
+    same_v = keep & ((gs & 8) == (os_ & 8))
+    cerr = np.abs(g["colour"][:, same_v] - o["colour"][:, same_v]).max(0) if same_v.any() else np.zeros(0)
+    stats["colour_ok"] = float(np.mean(cerr <= 2e-3)) if same_v.any() else 1.0
+    stats["colour_err_max"] = float(cerr.max()) if same_v.any() else 0.0
+    stats["shadow_agree"] = float(np.mean((gs[both] & 8) == (os_[both] & 8))) if both.any() else 1.0
+    gm = gid < 0
+    stats["miss_encoding_ok"] = bool(np.all(g["depth"][gm] == -1.0) and np.all(g["normal"][:, gm] == 0.0)
+                                     and np.all(g["colour"][:, gm] == 0.0))
+    return stats
+
+
+def assert_scene_parity(stats, id_agree=0.999, normal_ok=0.999):
+    msg = str(stats)
+    assert stats["id_agree"] >= id_agree, msg
+    assert stats["hit_agree"] >= id_agree, msg
+    assert stats["depth_ok"] >= 1.0, msg
+    assert stats["class_agree"] >= 1.0, msg
+    assert stats["normal_ok"] >= normal_ok, msg
+    assert stats["colour_ok"] >= normal_ok, msg
+    assert stats["miss_encoding_ok"], msg

@@ -52,13 +52,15 @@ def test_host_only_calls_without_gpu():
     assert b"kernel_variant" in L.frt_last_error()
     assert L.frt_autotune_set(0, 96, 256, 0, 8, 16) == frt.FRT_EINVAL
     assert L.frt_render_batch(None, 0, None, 0, 0, None) == frt.FRT_EINVAL
+    sa, sb = int(L.frt_scene_workspace_bytes(1)), int(L.frt_scene_workspace_bytes(16))
+    assert sa % 256 == 0 and sb % 256 == 0 and sb > sa > 1024
 
 
 def test_ctypes_layout_matches_c_header(tmp_path):
     import paper_2102_01747_amd as frt
 
     structs = {"frt_camera": frt.Camera, "frt_fractal": frt.Fractal, "frt_plane": frt.Plane,
-               "frt_march": frt.March, "frt_frame": frt.Frame, "frt_job": frt.Job}
+               "frt_march": frt.March, "frt_frame": frt.Frame, "frt_job": frt.Job, "frt_object": frt.Object}
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "frt.h"', "int main(void) {", 'printf("{");']
     first = True
     for cname, py in structs.items():

@@ -1,0 +1,148 @@
+"""Scenes of several fractal objects in one launch (Sec. 3, Fig. 4) and the
+iteration-count animation (Fig. 2) on the GPU, against the FP64 oracle:
+object ids, depth, normals and colours with shadows cast across objects,
+every kernel variant and normal mode; a single identity-placed object
+against the single-view renderer; argument validation.
+"""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from parity import (assert_parity, assert_scene_parity, compare, compare_scene, id_neighbour_flags,
+                    neighbour_flags, sampled_compare, to_numpy)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def frt():
+    import paper_2102_01747_amd as m
+    m.lib()
+    return m
+
+
+def _scene_parity(frt, orc, sc):
+    fr = frt.render_scene(sc, "cuda", counters=True)
+    torch.cuda.synchronize()
+    g = to_numpy(fr)
+    o = orc.render_scene(sc)
+    cam = sc["camera"]
+    H, W_ = cam["height"], cam["width"]
+    nd = id_neighbour_flags(o["object_id"].reshape(H, W_), o["status"].reshape(H, W_)).ravel()
+    st = compare_scene(orc, sc, g, o, nd)
+    print({k: len(sc["objects"]) for k in ["objects"]}, cam["width"], cam["height"], st, flush=True)
+    for k in range(len(sc["objects"])):
+        assert np.sum(o["object_id"] == k) > 200, k
+    assert_scene_parity(st)
+    return g, o
+
+
+def test_julia_bulb_scene(frt, orc):
+    _scene_parity(frt, orc, W.julia_bulb_scene())
+
+
+def test_overlap_scene_tetra(frt, orc):
+    g, o = _scene_parity(frt, orc, W.overlap_scene())
+    # shadows cast across objects are present on both sides
+    assert np.sum((g["status"] & 8) != 0) > 500
+
+
+@pytest.mark.parametrize("mode", ["central", "analytic"])
+def test_overlap_scene_normal_modes(frt, orc, mode):
+    _scene_parity(frt, orc, W.overlap_scene(width=200, height=150, normal_mode=mode))
+
+
+def test_scene_with_integer_and_degree_objects(frt, orc):
+    """Mandelbulb n = 5 (run-time integer power) and a degree-4 Julia with two
+    planes, both rotated and scaled, no shadows, ragged image size."""
+    objs = [W.scene_object(W.bulb(5.0, 10), rot=W.rotation([0.2, 1.0, 0.3], 2.0), translation=(-0.9, 0.2, 0.0),
+                           scale=0.8),
+            W.scene_object(W.julia([0.3, 0.5, 0.0, 0.2], 10, degree=4),
+                           planes=[W.plane([0.3, 0.2, 1.0], 0.05), W.plane([-1.0, 0.4, 0.2], 0.3)],
+                           rot=W.rotation([1.0, 0.0, 0.0], 0.7), translation=(0.9, -0.1, 0.3), scale=0.75)]
+    sc = W.scene(W.camera((0.0, 0.5, 4.0), 250, 130), objs, W.march(512, eps_rel=5e-4, t_max=20.0))
+    _scene_parity(frt, orc, sc)
+
+
+def test_identity_scene_equals_single_render(frt):
+    """One object placed by the identity: the scene kernel traces the same
+    rays with the same rules as the single-view kernels."""
+    jb = W.julia_view(width=200, height=160, planes=[W.plane([0.3, 0.2, 1.0], 0.05)], shadow=True)
+    sc = W.scene(jb["camera"], [W.scene_object(jb["fractal"], jb["planes"])], jb["march"])
+    a = to_numpy(frt.render(jb, "cuda"))
+    b = to_numpy(frt.render_scene(sc, "cuda"))
+    torch.cuda.synchronize()
+    # bit 6 marks the single renderer's shadow-ray work list; the scene has none
+    same = ((a["status"] & ~np.uint8(64)) == b["status"]) & (a["depth"] == b["depth"])
+    print("identical pixels: %.6f" % same.mean())
+    assert same.mean() > 0.999
+    assert np.array_equal(b["object_id"] >= 0, (a["status"] & 7) >= 2)
+
+
+def test_iteration_animation_batch(frt, orc):
+    """Fig. 2: ten frames whose orbit budget grows from 1 to 10, rendered in
+    one batch and compared frame by frame with the oracle."""
+    frames = W.iteration_animation(n_frames=10, width=320, height=180)
+    outs = frt.render_batch(frames, "cuda", counters=True)
+    torch.cuda.synchronize()
+    for k, (jb, fr) in enumerate(zip(frames, outs)):
+        g = to_numpy(fr)
+        o = orc.render(jb)
+        nd = neighbour_flags(o["status"].reshape(180, 320)).ravel()
+        st = compare(orc, jb, g, o, nd)
+        print("frame", k, "max_iter", jb["fractal"]["max_iter"], "hits", st["gpu_hits"], flush=True)
+        assert st["oracle_hits"] > 1000
+        assert_parity(st)
+
+
+def test_scene_1080p_throughput(frt, orc):
+    """The Julia + Mandelbulb scene at 1920x1080: timing, and a sampled
+    comparison of object ids with the oracle."""
+    sc = W.julia_bulb_scene(width=1920, height=1080)
+    fr = frt.render_scene(sc, "cuda")
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(5):
+        frt.render_scene(sc, "cuda", out=fr)
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / 5
+    print("scene 1920x1080, 2 objects, shadows: %.3f ms, %.0f Mrays/s" % (ms, 1920 * 1080 / (ms * 1e-3) / 1e6))
+    pix = W.stratified_pixels(1920, 1080, 16, seed=11)
+    o = orc.render_scene(sc, pixels=pix)
+    gid = fr["object_id"].cpu().numpy()[pix]
+    assert np.mean(gid == o["object_id"]) > 0.995
+
+
+def test_scene_rejects_bad_arguments(frt):
+    sc = W.julia_bulb_scene(width=16, height=16)
+    fr = frt.alloc_frame(sc, "cuda")
+    fr["depth"].fill_(7.0)
+    bad = []
+    s1 = copy.deepcopy(sc)
+    s1["objects"][1]["rotation"] = [1.0, 0.1, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0]   # not orthonormal
+    bad.append((s1, "rotation"))
+    s2 = copy.deepcopy(sc)
+    s2["objects"][0]["rotation"] = [-1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0]  # a reflection
+    bad.append((s2, "rotation"))
+    s3 = copy.deepcopy(sc)
+    s3["objects"][0]["scale"] = 0.0
+    bad.append((s3, "scale"))
+    s4 = copy.deepcopy(sc)
+    s4["objects"][1]["fractal"]["max_iter"] = 0
+    bad.append((s4, "object 1"))
+    s5 = copy.deepcopy(sc)
+    s5["objects"] = []
+    bad.append((s5, "n_objects"))
+    s6 = copy.deepcopy(sc)
+    s6["objects"] = [copy.deepcopy(sc["objects"][0]) for _ in range(17)]
+    bad.append((s6, "n_objects"))
+    for s_, what in bad:
+        with pytest.raises(frt.FrtError, match=what):
+            frt.render_scene(s_, "cuda", out=fr)
+    torch.cuda.synchronize()
+    assert torch.all(fr["depth"] == 7.0)
