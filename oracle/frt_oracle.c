@@ -83,6 +83,8 @@ typedef struct {
     int32_t normal_mode;   /* 0 tetrahedral (Eq. 5), 1 central differences, 2 analytic gradient */
     int32_t shadow;        /* 1: one shadow ray per lit hit                */
     double light[3], albedo[3], k_ambient, k_diffuse;
+    int32_t shading;       /* 0 Lambert; 1 Phong + Fresnel reflection (scenes, R23) */
+    double k_specular, shininess, k_reflect;
 } or_march;
 
 /* status classes (low 3 bits) and flags */
@@ -714,10 +716,13 @@ static int32_t count_crossings(const or_fractal* f, const or_march* mc, const do
 /* Primary part (trace_primary) of n explicit rays, origins and unit
  * directions [n][3], in the fractal's own frame and units: the building
  * block of scenes, whose objects the caller places by similarity maps.
- * normal is [n][3]; lt the last-but-one sample; crossings (when samples > 0)
- * the sign changes of d - eps over the final bracket of refinable hits.    */
+ * eps0 (may be NULL) gives each ray its own eps_abs, which is also where it
+ * starts (reflection rays).  normal is [n][3]; lt the last-but-one sample;
+ * crossings (when samples > 0) the sign changes of d - eps over the final
+ * bracket of refinable hits.                                                */
 int oracle_trace_rays(const or_fractal* f, const or_plane* planes, int32_t n_planes, const or_march* mc,
-                      const double* orig, const double* dirs, int64_t n, int32_t samples, uint8_t* status,
+                      const double* orig, const double* dirs, const double* eps0, int64_t n, int32_t samples,
+                      uint8_t* status,
                       double* depth, double* normal, int32_t* steps, int32_t* hit_iters, double* raw_t, double* lt,
                       int32_t* crossings, int64_t* de_evals, int64_t* orbit_bodies) {
     if (!f || !mc || !orig || !dirs) return -1;
@@ -727,7 +732,9 @@ int oracle_trace_rays(const or_fractal* f, const or_plane* planes, int32_t n_pla
     for (int64_t q = 0; q < n; ++q) {
         pixel_result px;
         double l;
-        trace_primary(f, planes, n_planes, mc, orig + 3 * q, dirs + 3 * q, &px, &l);
+        or_march m = *mc;
+        if (eps0) m.eps_abs = eps0[q];
+        trace_primary(f, planes, n_planes, &m, orig + 3 * q, dirs + 3 * q, &px, &l);
         if (status) status[q] = (uint8_t)px.status;
         if (depth) depth[q] = px.depth;
         if (normal) for (int k = 0; k < 3; ++k) normal[3 * q + k] = px.normal[k];
@@ -737,7 +744,7 @@ int oracle_trace_rays(const or_fractal* f, const or_plane* planes, int32_t n_pla
         if (lt) lt[q] = l;
         if (crossings) {
             crossings[q] = ((px.status & 7) == ST_HIT && l >= 0.0 && samples > 0)
-                               ? count_crossings(f, mc, orig + 3 * q, dirs + 3 * q, l, px.raw_t, samples)
+                               ? count_crossings(f, &m, orig + 3 * q, dirs + 3 * q, l, px.raw_t, samples)
                                : 0;
         }
         if (de_evals) de_evals[q] = px.de_evals;
@@ -803,6 +810,45 @@ int32_t oracle_max_threads(void) {
 #else
     return 1;
 #endif
+}
+
+/* Orbit trap at points (R24): over the orbit of the estimate at p (the
+ * start point and the result of every body run, the escaping one included)
+ * the minima of |x|, |y|, |z| (the first three quaternion components for
+ * Julia) and of the squared norm.  out is [n][4].                          */
+void oracle_trap(const or_fractal* f, const double* pts, int64_t n, double* out) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        const double* p = pts + 3 * i;
+        double tr[4] = { fabs(p[0]), fabs(p[1]), fabs(p[2]), dot3(p, p) };
+        if (f->kind == 0) {
+            double z[4] = { p[0], p[1], p[2], 0.0 };
+            int32_t deg = julia_degree(f);
+            for (int32_t k = 0; k < f->max_iter; ++k) {
+                double zp[4];
+                oracle_quat_pow(z, deg, zp);
+                for (int c = 0; c < 4; ++c) z[c] = zp[c] + f->c[c];
+                double m2 = qlen2(z);
+                tr[0] = fmin(tr[0], fabs(z[0])); tr[1] = fmin(tr[1], fabs(z[1])); tr[2] = fmin(tr[2], fabs(z[2]));
+                tr[3] = fmin(tr[3], m2);
+                if (m2 > f->bailout2) break;
+            }
+        } else {
+            double w[3] = { p[0], p[1], p[2] };
+            for (int32_t k = 0; k < f->max_iter; ++k) {
+                double wn[3];
+                oracle_bulb_power(w, f->power, wn);
+                for (int c = 0; c < 3; ++c) w[c] = wn[c] + p[c];
+                double m = dot3(w, w);
+                tr[0] = fmin(tr[0], fabs(w[0])); tr[1] = fmin(tr[1], fabs(w[1])); tr[2] = fmin(tr[2], fabs(w[2]));
+                tr[3] = fmin(tr[3], m);
+                if (m > f->bailout2) break;
+            }
+        }
+        for (int c = 0; c < 4; ++c) out[4 * i + c] = tr[c];
+    }
 }
 
 /* Final march bracket of listed pixels (R9): for a refinable surface hit the

@@ -25,8 +25,10 @@ STATUS_HIT_EXHAUSTED = 4
 FLAG_SHADOWED = 8
 FLAG_UNREFINED = 16
 FLAG_JUMP = 32          # oracle only: the root bracket closed on a jump of the estimate
+FLAG_REFLECT_HIT = 128  # scenes with the closest-hit shading: the reflection ray hit an object
 
 NORMAL_MODES = {"tetra": 0, "central": 1, "analytic": 2}
+SHADING_MODELS = {"lambert": 0, "phong": 1}
 
 # Jacobian column slots (see oracle_pixel_jacobian)
 SLOT_C = slice(0, 4)
@@ -54,7 +56,9 @@ class March(ctypes.Structure):
                 ("step_clamp", ctypes.c_double), ("t_max", ctypes.c_double),
                 ("normal_mode", ctypes.c_int32), ("shadow", ctypes.c_int32),
                 ("light", c_double3), ("albedo", c_double3),
-                ("k_ambient", ctypes.c_double), ("k_diffuse", ctypes.c_double)]
+                ("k_ambient", ctypes.c_double), ("k_diffuse", ctypes.c_double),
+                ("shading", ctypes.c_int32), ("k_specular", ctypes.c_double), ("shininess", ctypes.c_double),
+                ("k_reflect", ctypes.c_double)]
 
 
 _lib = None
@@ -90,7 +94,7 @@ def lib():
                                             dp, P(ctypes.c_int32)]
         L.oracle_pixel_jacobian.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int32
-        L.oracle_trace_rays.argtypes = [P(Fractal), P(Plane), ctypes.c_int32, P(March), dp, dp, ctypes.c_int64,
+        L.oracle_trace_rays.argtypes = [P(Fractal), P(Plane), ctypes.c_int32, P(March), dp, dp, dp, ctypes.c_int64,
                                         ctypes.c_int32, P(ctypes.c_uint8), dp, dp, P(ctypes.c_int32),
                                         P(ctypes.c_int32), dp, dp, P(ctypes.c_int32), P(ctypes.c_int64),
                                         P(ctypes.c_int64)]
@@ -98,6 +102,7 @@ def lib():
         L.oracle_occluded.argtypes = [P(Fractal), P(Plane), ctypes.c_int32, P(March), dp, dp, dp, ctypes.c_int64,
                                       P(ctypes.c_uint8)]
         L.oracle_occluded.restype = ctypes.c_int
+        L.oracle_trap.argtypes = [P(Fractal), dp, ctypes.c_int64, dp]
         L.oracle_bracket_crossings.argtypes = [P(Camera), P(Fractal), P(Plane), ctypes.c_int32, P(March),
                                                P(ctypes.c_int64), ctypes.c_int64, ctypes.c_int32, dp, dp,
                                                P(ctypes.c_int32)]
@@ -142,7 +147,9 @@ def make_march(m):
     mode = NORMAL_MODES[m["normal_mode"]]
     return March(int(m["max_steps"]), float(m["eps_abs"]), float(m["eps_rel"]), float(m["step_clamp"]),
                  float(m["t_max"]), mode, int(bool(m["shadow"])), c_double3(*m["light_dir"]),
-                 c_double3(*m["albedo"]), float(m["k_ambient"]), float(m["k_diffuse"]))
+                 c_double3(*m["albedo"]), float(m["k_ambient"]), float(m["k_diffuse"]),
+                 SHADING_MODELS[m.get("shading", "lambert")], float(m.get("k_specular", 0.0)),
+                 float(m.get("shininess", 1.0)), float(m.get("k_reflect", 0.0)))
 
 
 def max_threads():
@@ -156,6 +163,8 @@ def render(job, pixels=None, threads=0):
     status [n] (uint8), steps [n], hit_iters [n], de_evals [n],
     orbit_bodies [n], raw_t [n].
     """
+    if job["march"].get("shading", "lambert") != "lambert":
+        raise ValueError("the closest-hit shading model is defined for scenes (render_scene)")
     L = lib()
     cam, fr, mc = make_camera(job["camera"]), make_fractal(job["fractal"]), make_march(job["march"])
     pl, npl = make_planes(job.get("planes", []))
@@ -350,9 +359,10 @@ def normal_perturbed(fractal, points, dirs, eps, mode, rel, seed):
 
 
 # ---------------------------------------------------------------- scenes
-def trace_rays(fractal, planes, march, origins, dirs, samples=0):
+def trace_rays(fractal, planes, march, origins, dirs, samples=0, eps0=None):
     """Primary part (march, refinement, normal; no shading) of explicit rays
-    in the fractal's own frame and units.  Returns status, depth, normal
+    in the fractal's own frame and units; eps0 [n] optionally sets each
+    ray's eps_abs (and start).  Returns status, depth, normal
     [n, 3], steps, hit_iters, raw_t, lt (last-but-one sample), crossings
     (sign changes of d - eps over the final bracket, if samples > 0)."""
     L = lib()
@@ -361,12 +371,14 @@ def trace_rays(fractal, planes, march, origins, dirs, samples=0):
     o = np.ascontiguousarray(origins, dtype=np.float64).reshape(-1, 3)
     d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
     n = o.shape[0]
+    e0 = None if eps0 is None else np.ascontiguousarray(np.broadcast_to(eps0, (n,)), dtype=np.float64)
     out = {"status": np.empty(n, np.uint8), "depth": np.empty(n), "normal": np.empty((n, 3)),
            "steps": np.empty(n, np.int32), "hit_iters": np.empty(n, np.int32), "raw_t": np.empty(n),
            "lt": np.empty(n), "crossings": np.zeros(n, np.int32), "de_evals": np.empty(n, np.int64),
            "orbit_bodies": np.empty(n, np.int64)}
     rc = L.oracle_trace_rays(ctypes.byref(fr), pl, npl, ctypes.byref(mc), _ptr(o, ctypes.c_double),
-                             _ptr(d, ctypes.c_double), n, int(samples), _ptr(out["status"], ctypes.c_uint8),
+                             _ptr(d, ctypes.c_double), _ptr(e0, ctypes.c_double), n, int(samples),
+                             _ptr(out["status"], ctypes.c_uint8),
                              _ptr(out["depth"], ctypes.c_double), _ptr(out["normal"], ctypes.c_double),
                              _ptr(out["steps"], ctypes.c_int32), _ptr(out["hit_iters"], ctypes.c_int32),
                              _ptr(out["raw_t"], ctypes.c_double), _ptr(out["lt"], ctypes.c_double),
@@ -470,9 +482,66 @@ def render_scene(scene, pixels=None, samples=0):
             shadowed[idx[hit_k]] = True
         vis[lit[shadowed]] = 0.0
         status[lit[shadowed]] |= FLAG_SHADOWED
+    albedo = np.array(mc["albedo"], dtype=np.float64)
     lam = mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0.0, ndl) * vis
-    colour = np.where(hit[None, :], np.array(mc["albedo"], dtype=np.float64)[:, None] * lam[None, :], 0.0)
+    colour = albedo[:, None] * lam[None, :]
+    if mc.get("shading", "lambert") == "phong":
+        # R23: white Phong highlight (shadowed with the diffuse term), then one
+        # reflection bounce weighted by Schlick's Fresnel term with f0 = albedo
+        colour = colour + float(mc["k_specular"]) * _phong_spec(nrm, Ld, -d, ndl, float(mc["shininess"]))[None, :] * vis
+        h = np.nonzero(hit)[0]
+        eps_s = mc["eps_abs"] + mc["eps_rel"] * depth[h]
+        dn = np.einsum("ij,ij->i", d[h], nrm[h])
+        rd = d[h] - 2.0 * dn[:, None] * nrm[h]
+        q = o[h] + depth[h, None] * d[h] + 4.0 * eps_s[:, None] * nrm[h]
+        rt = np.full(h.size, np.inf)
+        rn = np.zeros((h.size, 3))
+        for ob in scene["objects"]:
+            R, T, s = object_frame(ob)
+            r = trace_rays(ob["fractal"], ob.get("planes", []), object_march(mc, s), (q - T) @ R / s, rd @ R,
+                           eps0=eps_s / s)
+            tw = r["depth"] * s
+            better = ((r["status"] & 7) >= STATUS_HIT) & (tw < rt)
+            rt[better] = tw[better]
+            rn[better] = r["normal"][better] @ R.T
+        rhit = np.isfinite(rt)
+        rl = np.linalg.norm(rn, axis=1, keepdims=True)
+        rn = np.where(rl > 0, rn / np.where(rl > 0, rl, 1.0), rn)
+        rndl = rn @ Ld
+        c_r = albedo[:, None] * (mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0.0, rndl))[None, :]
+        c_r = c_r + float(mc["k_specular"]) * _phong_spec(rn, Ld, -rd, rndl, float(mc["shininess"]))[None, :]
+        c_r = np.where(rhit[None, :], c_r, 0.0)
+        cos_i = np.maximum(0.0, -dn)
+        F = albedo[:, None] + (1.0 - albedo[:, None]) * ((1.0 - cos_i) ** 5)[None, :]
+        colour[:, h] += float(mc["k_reflect"]) * F * c_r
+        status[h[rhit]] |= FLAG_REFLECT_HIT
+    colour = np.where(hit[None, :], colour, 0.0)
+    # orbit trap (R24) at the hit point, in the object's frame
+    trap = np.zeros((4, n))
+    for k, ob in enumerate(scene["objects"]):
+        m = np.nonzero(best == k)[0]
+        if m.size:
+            R, T, s = object_frame(ob)
+            trap[:, m] = orbit_trap(ob["fractal"], (o[m] + depth[m, None] * d[m] - T) @ R / s).T
     out = {"depth": depth, "normal": np.where(hit[None, :], nrm.T, 0.0), "colour": colour, "status": status,
-           "object_id": best}
+           "object_id": best, "trap": trap}
     out.update(keep)
+    return out
+
+
+def _phong_spec(nrm, L, V, ndl, shininess):
+    """max(0, R.V)^shininess with R = 2 (N.L) N - L the mirrored light
+    direction, zero where the light is behind the surface."""
+    Rl = 2.0 * ndl[:, None] * nrm - L[None, :]
+    return np.where(ndl > 0.0, np.maximum(0.0, np.einsum("ij,ij->i", Rl, V)) ** shininess, 0.0)
+
+
+def orbit_trap(fractal, points):
+    """Orbit trap at points [n, 3] (R24): [n, 4] minima over the orbit of
+    |x|, |y|, |z| and the squared norm."""
+    L = lib()
+    fr = make_fractal(fractal)
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    out = np.empty((pts.shape[0], 4))
+    L.oracle_trap(ctypes.byref(fr), _ptr(pts, ctypes.c_double), pts.shape[0], _ptr(out, ctypes.c_double))
     return out

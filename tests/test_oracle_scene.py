@@ -137,3 +137,110 @@ def test_iteration_animation_frames(orc):
     outs = [orc.render(f) for f in frames]
     assert all(((o["status"] & 7) >= 2).sum() > 500 for o in outs)
     assert all(not np.array_equal(a["depth"], b["depth"]) for a, b in zip(outs, outs[1:]))
+
+
+# ------------------------------------------------ closest-hit shading (R23)
+def _ball(translation, scale):
+    fr = W.julia([0, 0, 0, 0], 11, bound_radius=1.5)
+    return W.scene_object(fr, translation=translation, scale=scale)
+
+
+def _rho(eps):
+    from scipy.optimize import brentq
+    import math
+    return brentq(lambda r: 0.5 * r * math.log(r) - eps, 1.0, 2.0, xtol=1e-15)
+
+
+def _phong_closed(N, L, V, albedo, mc):
+    ndl = N @ L
+    Rl = 2.0 * ndl[:, None] * N - L
+    spec = np.where(ndl > 0, np.maximum(0.0, np.einsum("ij,ij->i", Rl, V)) ** mc["shininess"], 0.0)
+    return albedo[:, None] * (mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0, ndl))[None, :] + \
+        mc["k_specular"] * spec[None, :]
+
+
+def test_phong_on_the_c0_ball_is_closed_form(orc):
+    """One c = 0 ball (convex: no reflection ray comes back to it): colour is
+    the Phong term of the radial normal, no pixel reports a reflection hit."""
+    mc = W.phong(W.march(256, eps_abs=1e-3, normal_mode="analytic"))
+    sc = W.scene(W.camera((0.3, 0.8, 3.0), 96, 96), [_ball((0.0, 0.0, 0.0), 1.0)], mc)
+    out = orc.render_scene(sc)
+    hit = np.nonzero(out["object_id"] == 0)[0]
+    assert hit.size > 1000
+    assert not np.any(out["status"] & orc.FLAG_REFLECT_HIT)
+    o, d = orc.camera_rays(sc["camera"], hit)
+    p = o + out["depth"][hit, None] * d
+    N = p / np.linalg.norm(p, axis=1, keepdims=True)
+    L = np.array(mc["light_dir"], dtype=np.float64)
+    L /= np.linalg.norm(L)
+    ref = _phong_closed(N, L, -d, np.array(mc["albedo"], dtype=np.float64), mc)
+    assert np.abs(out["colour"][:, hit] - ref).max() < 1e-6
+
+
+def test_reflection_between_two_balls_is_closed_form(orc):
+    """Two c = 0 balls (radius s rho_eps): where a reflection ray from ball A
+    meets ball B (ray-sphere intersection in closed form), the colour is
+    A's Phong term plus 0.1 Schlick(f0 = albedo) times B's Phong term at the
+    intersection; elsewhere the reflection adds nothing."""
+    mc = W.phong(W.march(256, eps_abs=1e-3, t_max=20.0, normal_mode="analytic"))
+    A, B = (-0.7, 0.0, 0.0), (0.75, 0.1, -0.3)
+    sA, sB = 0.6, 0.5
+    sc = W.scene(W.camera((0.0, 0.3, 3.0), 128, 96), [_ball(A, sA), _ball(B, sB)], mc)
+    out = orc.render_scene(sc)
+    pix = np.nonzero(out["object_id"] == 0)[0]
+    o, d = orc.camera_rays(sc["camera"], pix)
+    t = out["depth"][pix]
+    Av, Bv = np.array(A, dtype=np.float64), np.array(B, dtype=np.float64)
+    p = o + t[:, None] * d
+    N = (p - Av) / np.linalg.norm(p - Av, axis=1, keepdims=True)
+    L = np.array(mc["light_dir"], dtype=np.float64)
+    L /= np.linalg.norm(L)
+    albedo = np.array(mc["albedo"], dtype=np.float64)
+    base = _phong_closed(N, L, -d, albedo, mc)
+    # reflected ray against B's eps-level sphere (world radius sB rho(eps_B))
+    eps_s = mc["eps_abs"] + 0.0 * t
+    dn = np.einsum("ij,ij->i", d, N)
+    rd = d - 2 * dn[:, None] * N
+    q = p + 4 * eps_s[:, None] * N
+    # in B's frame the level set sits where 0.5 r ln r = eps_s / sB (eps_rel = 0)
+    rB = np.array([sB * _rho(e / sB) for e in eps_s])
+    oc = q - Bv
+    bq = np.einsum("ij,ij->i", oc, rd)
+    disc = bq ** 2 - (np.einsum("ij,ij->i", oc, oc) - rB ** 2)
+    meets = disc > 0
+    th = np.where(meets, -bq - np.sqrt(np.maximum(disc, 0)), np.inf)
+    meets &= th > 0
+    clear = np.abs(disc) > 1e-3                        # away from B's silhouette
+    assert np.sum(meets & clear) > 30
+    hp = q + np.where(meets, th, 0.0)[:, None] * rd
+    NB = (hp - Bv) / np.linalg.norm(hp - Bv, axis=1, keepdims=True)
+    c_r = _phong_closed(np.where(meets[:, None], NB, 0.0), L, -rd, albedo, mc)
+    F = albedo[:, None] + (1 - albedo[:, None]) * ((1 - np.maximum(0, -dn)) ** 5)[None, :]
+    ref = base + np.where(meets[None, :], mc["k_reflect"] * F * c_r, 0.0)
+    flag = (out["status"][pix] & orc.FLAG_REFLECT_HIT) != 0
+    assert np.array_equal(flag[clear], meets[clear])
+    assert np.abs(out["colour"][:, pix][:, clear] - ref[:, clear]).max() < 1e-5
+
+
+def test_orbit_trap_of_c0_julia_is_closed_form(orc):
+    """c = 0, degree 2: z_k = z^(2^k) stays in the complex plane span{1, v};
+    its components are Re(zeta^(2^k)) and Im(zeta^(2^k)) v_hat with
+    zeta = x + i|v|, so the trap follows from complex powers."""
+    rng = np.random.default_rng(90)
+    pts = rng.normal(size=(300, 3))
+    pts *= (rng.uniform(0.7, 1.3, size=300) / np.linalg.norm(pts, axis=1))[:, None]
+    fr = W.julia([0, 0, 0, 0], 6)
+    got = orc.orbit_trap(fr, pts)
+    for p, g in zip(pts, got):
+        v = p[1:]
+        vn = np.linalg.norm(v)
+        zeta = complex(p[0], vn)
+        tr = [abs(p[0]), abs(p[1]), abs(p[2]), p @ p]
+        z = zeta
+        for _ in range(6):
+            z = z * z
+            comp = [abs(z.real), abs(z.imag * v[0] / vn), abs(z.imag * v[1] / vn), abs(z) ** 2]
+            tr = [min(a, b) for a, b in zip(tr, comp)]
+            if abs(z) ** 2 > 256.0:
+                break
+        np.testing.assert_allclose(g, tr, rtol=1e-9, atol=1e-12)

@@ -46,11 +46,28 @@ def orbit_eye(radius, azimuth, elevation):
 
 
 def march(max_steps, eps_abs=0.0, eps_rel=0.0, normal_mode="tetra", shadow=False, step_clamp=0.2,
-          t_max=7000.0, refine_iters=12):
+          t_max=7000.0, refine_iters=12, shading="lambert", k_specular=0.0, shininess=1.0, k_reflect=0.0):
     return {"max_steps": int(max_steps), "eps_abs": f32(eps_abs), "eps_rel": f32(eps_rel),
             "step_clamp": f32(step_clamp), "t_max": f32(t_max), "normal_mode": normal_mode,
             "refine_iters": int(refine_iters), "shadow": bool(shadow), "light_dir": list(LIGHT_DIR),
-            "albedo": list(ALBEDO), "k_ambient": K_AMBIENT, "k_diffuse": K_DIFFUSE}
+            "albedo": list(ALBEDO), "k_ambient": K_AMBIENT, "k_diffuse": K_DIFFUSE, "shading": shading,
+            "k_specular": f32(k_specular), "shininess": f32(shininess), "k_reflect": f32(k_reflect)}
+
+
+# The closest-hit shading of the paper's shaders (Phong highlight, one
+# reflection bounce with Schlick's Fresnel term; reflection weight 0.1 as in
+# the Julia closest-hit listing), with a coloured albedo so that the Fresnel
+# term's f0 differs per channel.
+PHONG = {"shading": "phong", "k_specular": 0.5, "shininess": 40.0, "k_reflect": 0.1}
+PHONG_ALBEDO = f32v([0.9, 0.6, 0.3])
+
+
+def phong(mc):
+    """A march dict switched to the closest-hit shading."""
+    out = dict(mc)
+    out.update({k: (f32(v) if isinstance(v, float) else v) for k, v in PHONG.items()})
+    out["albedo"] = list(PHONG_ALBEDO)
+    return out
 
 
 def julia(c, max_iter, bailout2=256.0, bound_radius=0.0, degree=2):
