@@ -68,6 +68,7 @@ typedef enum {
 
 enum { FRT_JULIA = 0, FRT_MANDELBULB = 1 };
 enum { FRT_NORMAL_TETRA = 0, FRT_NORMAL_CENTRAL = 1, FRT_NORMAL_ANALYTIC = 2 };
+enum { FRT_SHADING_LAMBERT = 0, FRT_SHADING_PHONG = 1 };
 
 /* Pinhole camera: vertical field of view, pixel centres, row 0 at the top.
  * Ray through pixel (i, j): dir = normalize(f + x r + y u) with
@@ -122,7 +123,16 @@ typedef struct {
  * colour = albedo (k_ambient + k_diffuse max(0, N.L) V), L = light_dir
  * normalised, V = 0 when the shadow ray (from p* + 4 eps(t*) N toward L,
  * threshold eps(t*)) hits, else 1; V is traced only when shadow != 0 and
- * N.L > 0.                                                                 */
+ * N.L > 0.
+ * FRT_SHADING_PHONG, the closest-hit shading of the paper's shaders, is
+ * served by frt_render_scene only (the other renderers return
+ * FRT_EUNSUPPORTED): the colour above plus a white highlight
+ * k_specular max(0, R.V)^shininess V (R = 2 (N.L) N - L, V = -dir, zero when
+ * N.L <= 0), plus k_reflect F c_r, where c_r is the colour of the first hit
+ * of the reflection ray (from p* + 4 eps(t*) N along dir - 2 (dir.N) N,
+ * threshold eps(t*) + eps_rel s at distance s, against every object; its
+ * own Lambert and highlight terms, no shadow ray; 0 on a miss) and
+ * F = albedo + (1 - albedo)(1 - max(0, -dir.N))^5 (Schlick, per channel).  */
 typedef struct {
     int32_t max_steps;          /* [1, 65536]                                */
     float eps_abs, eps_rel;     /* >= 0, not both 0                          */
@@ -134,6 +144,11 @@ typedef struct {
     float light_dir[3];         /* non-zero                                  */
     float albedo[3];
     float k_ambient, k_diffuse;
+    int32_t shading;            /* FRT_SHADING_LAMBERT, or _PHONG (scenes)   */
+    float k_specular;           /* >= 0 (Phong highlight weight)             */
+    float shininess;            /* [1, 10000] (Phong exponent)               */
+    float k_reflect;            /* [0, 1] (reflection weight); these three   */
+                                /* are read only with FRT_SHADING_PHONG      */
 } frt_march;
 
 /* Output planes (device pointers, see the layout above).  depth, normal,
@@ -256,12 +271,19 @@ size_t frt_scene_workspace_bytes(int32_t n_objects);
  * a miss), 4-5 its normal, 6-7 the shadow ray over all objects.  A miss is
  * a t_max miss when the ray entered any object's interval, else a bounds
  * miss.  object_id: int32[H*W] (device, may be NULL) receives the index of
- * the object hit, -1 on a miss.
+ * the object hit, -1 on a miss.  trap: float[4][H*W] (device, may be NULL)
+ * receives the orbit trap at the hit point in the object's frame (the
+ * colour parameters of the Mandelbulb distance listing, defined here as the
+ * minima of |x|, |y|, |z| and |w|^2 over the start point and every body of
+ * the estimate's orbit; Julia: the first three quaternion components), 0 on
+ * a miss.  With FRT_SHADING_PHONG, status bit 7 (128) marks pixels whose
+ * reflection ray hit an object, and counter planes 6-7 count the shadow and
+ * reflection rays together.
  * Errors: FRT_EINVAL (nothing launched) for invalid parameters, naming the
  * object; FRT_ENOMEM for a small workspace; FRT_EHIP for a failed launch. */
 frt_status frt_render_scene(const frt_camera* cam, const frt_object* objects, int32_t n_objects,
-                            const frt_march* march, frt_frame out, int32_t* object_id, void* workspace,
-                            size_t ws_bytes, void* stream);
+                            const frt_march* march, frt_frame out, int32_t* object_id, float* trap,
+                            void* workspace, size_t ws_bytes, void* stream);
 
 /* Distance estimate (Sec. 2, Eq. 2-4) at n points, the same orbit code the
  * renderer marches with: points float[n][3] (device), d float[n] (device),

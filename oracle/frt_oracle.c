@@ -816,39 +816,52 @@ int32_t oracle_max_threads(void) {
  * start point and the result of every body run, the escaping one included)
  * the minima of |x|, |y|, |z| (the first three quaternion components for
  * Julia) and of the squared norm.  out is [n][4].                          */
+static void trap_at(const or_fractal* f, const double p[3], double rel, uint64_t seed, uint64_t key,
+                    double tr[4]) {
+    tr[0] = fabs(p[0]); tr[1] = fabs(p[1]); tr[2] = fabs(p[2]); tr[3] = dot3(p, p);
+    if (f->kind == 0) {
+        double z[4] = { p[0], p[1], p[2], 0.0 };
+        int32_t deg = julia_degree(f);
+        for (int32_t k = 0; k < f->max_iter; ++k) {
+            double zp[4];
+            oracle_quat_pow(z, deg, zp);
+            for (int c = 0; c < 4; ++c)
+                z[c] = (rel != 0.0 ? zp[c] * noise(seed, key, k, c, rel) : zp[c]) + f->c[c];
+            double m2 = qlen2(z);
+            tr[0] = fmin(tr[0], fabs(z[0])); tr[1] = fmin(tr[1], fabs(z[1])); tr[2] = fmin(tr[2], fabs(z[2]));
+            tr[3] = fmin(tr[3], m2);
+            if (m2 > f->bailout2) break;
+        }
+    } else {
+        double w[3] = { p[0], p[1], p[2] };
+        for (int32_t k = 0; k < f->max_iter; ++k) {
+            double wn[3];
+            oracle_bulb_power(w, f->power, wn);
+            for (int c = 0; c < 3; ++c)
+                w[c] = (rel != 0.0 ? wn[c] * noise(seed, key, k, c, rel) : wn[c]) + p[c];
+            double m = dot3(w, w);
+            tr[0] = fmin(tr[0], fabs(w[0])); tr[1] = fmin(tr[1], fabs(w[1])); tr[2] = fmin(tr[2], fabs(w[2]));
+            tr[3] = fmin(tr[3], m);
+            if (m > f->bailout2) break;
+        }
+    }
+}
+
 void oracle_trap(const or_fractal* f, const double* pts, int64_t n, double* out) {
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 256)
 #endif
-    for (int64_t i = 0; i < n; ++i) {
-        const double* p = pts + 3 * i;
-        double tr[4] = { fabs(p[0]), fabs(p[1]), fabs(p[2]), dot3(p, p) };
-        if (f->kind == 0) {
-            double z[4] = { p[0], p[1], p[2], 0.0 };
-            int32_t deg = julia_degree(f);
-            for (int32_t k = 0; k < f->max_iter; ++k) {
-                double zp[4];
-                oracle_quat_pow(z, deg, zp);
-                for (int c = 0; c < 4; ++c) z[c] = zp[c] + f->c[c];
-                double m2 = qlen2(z);
-                tr[0] = fmin(tr[0], fabs(z[0])); tr[1] = fmin(tr[1], fabs(z[1])); tr[2] = fmin(tr[2], fabs(z[2]));
-                tr[3] = fmin(tr[3], m2);
-                if (m2 > f->bailout2) break;
-            }
-        } else {
-            double w[3] = { p[0], p[1], p[2] };
-            for (int32_t k = 0; k < f->max_iter; ++k) {
-                double wn[3];
-                oracle_bulb_power(w, f->power, wn);
-                for (int c = 0; c < 3; ++c) w[c] = wn[c] + p[c];
-                double m = dot3(w, w);
-                tr[0] = fmin(tr[0], fabs(w[0])); tr[1] = fmin(tr[1], fabs(w[1])); tr[2] = fmin(tr[2], fabs(w[2]));
-                tr[3] = fmin(tr[3], m);
-                if (m > f->bailout2) break;
-            }
-        }
-        for (int c = 0; c < 4; ++c) out[4 * i + c] = tr[c];
-    }
+    for (int64_t i = 0; i < n; ++i) trap_at(f, pts + 3 * i, 0.0, 0, 0, out + 4 * i);
+}
+
+/* The trap with the rounding probe of perturbed_de on every power: a
+ * conditioning check of the trap at float32 resolution.                    */
+void oracle_trap_perturbed(const or_fractal* f, const double* pts, int64_t n, double rel, uint64_t seed,
+                           double* out) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < n; ++i) trap_at(f, pts + 3 * i, rel, seed, (uint64_t)i, out + 4 * i);
 }
 
 /* Final march bracket of listed pixels (R9): for a refinable surface hit the

@@ -103,6 +103,7 @@ def lib():
                                       P(ctypes.c_uint8)]
         L.oracle_occluded.restype = ctypes.c_int
         L.oracle_trap.argtypes = [P(Fractal), dp, ctypes.c_int64, dp]
+        L.oracle_trap_perturbed.argtypes = [P(Fractal), dp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, dp]
         L.oracle_bracket_crossings.argtypes = [P(Camera), P(Fractal), P(Plane), ctypes.c_int32, P(March),
                                                P(ctypes.c_int64), ctypes.c_int64, ctypes.c_int32, dp, dp,
                                                P(ctypes.c_int32)]
@@ -534,6 +535,18 @@ def _phong_spec(nrm, L, V, ndl, shininess):
     direction, zero where the light is behind the surface."""
     Rl = 2.0 * ndl[:, None] * nrm - L[None, :]
     return np.where(ndl > 0.0, np.maximum(0.0, np.einsum("ij,ij->i", Rl, V)) ** shininess, 0.0)
+
+
+def orbit_trap_perturbed(fractal, points, rel, seed):
+    """The orbit trap with every power perturbed by a relative
+    uniform(-rel, rel) factor per component (seeded): a rounding probe."""
+    L = lib()
+    fr = make_fractal(fractal)
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    out = np.empty((pts.shape[0], 4))
+    L.oracle_trap_perturbed(ctypes.byref(fr), _ptr(pts, ctypes.c_double), pts.shape[0], float(rel), int(seed),
+                            _ptr(out, ctypes.c_double))
+    return out
 
 
 def orbit_trap(fractal, points):

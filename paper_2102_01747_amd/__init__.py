@@ -21,6 +21,8 @@ FRT_OK, FRT_EINVAL, FRT_EHIP, FRT_ENOMEM, FRT_EUNSUPPORTED = 0, -1, -2, -3, -4
 STATUS_MISS_BOUNDS, STATUS_MISS_TMAX, STATUS_HIT, STATUS_HIT_CUT, STATUS_HIT_EXHAUSTED = 0, 1, 2, 3, 4
 FLAG_SHADOWED, FLAG_UNREFINED, FLAG_SHADOW_RAY = 8, 16, 64
 NORMAL_MODES = {"tetra": 0, "central": 1, "analytic": 2}
+SHADING_MODELS = {"lambert": 0, "phong": 1}
+FLAG_REFLECT_HIT = 128
 VARIANTS = {"julia": 0, "bulb_real": 1, "bulb_int": 2, "bulb8": 3, "julia_deg": 4}
 
 f3 = ctypes.c_float * 3
@@ -49,7 +51,8 @@ class March(ctypes.Structure):
     _fields_ = [("max_steps", ctypes.c_int32), ("eps_abs", ctypes.c_float), ("eps_rel", ctypes.c_float),
                 ("step_clamp", ctypes.c_float), ("t_max", ctypes.c_float), ("normal_mode", ctypes.c_int32),
                 ("refine_iters", ctypes.c_int32), ("shadow", ctypes.c_int32), ("light_dir", f3), ("albedo", f3),
-                ("k_ambient", ctypes.c_float), ("k_diffuse", ctypes.c_float)]
+                ("k_ambient", ctypes.c_float), ("k_diffuse", ctypes.c_float), ("shading", ctypes.c_int32),
+                ("k_specular", ctypes.c_float), ("shininess", ctypes.c_float), ("k_reflect", ctypes.c_float)]
 
 
 class Frame(ctypes.Structure):
@@ -98,7 +101,7 @@ def lib():
         L.frt_normal_at.argtypes = [P(Fractal), i32, vp, vp, ctypes.c_int64, vp, vp]
         L.frt_scene_workspace_bytes.argtypes = [i32]
         L.frt_scene_workspace_bytes.restype = ctypes.c_size_t
-        L.frt_render_scene.argtypes = [P(Camera), P(Object), i32, P(March), Frame, vp, vp, ctypes.c_size_t, vp]
+        L.frt_render_scene.argtypes = [P(Camera), P(Object), i32, P(March), Frame, vp, vp, vp, ctypes.c_size_t, vp]
         L.frt_render_scene.restype = ctypes.c_int
         L.frt_normal_at.restype = ctypes.c_int
         L.frt_math_eval.argtypes = [i32, vp, vp, vp, ctypes.c_int64, vp]
@@ -164,7 +167,9 @@ def make_march(m):
     mode = NORMAL_MODES[m["normal_mode"]] if isinstance(m["normal_mode"], str) else int(m["normal_mode"])
     return March(int(m["max_steps"]), float(m["eps_abs"]), float(m["eps_rel"]), float(m["step_clamp"]),
                  float(m["t_max"]), mode, int(m.get("refine_iters", 12)), int(bool(m["shadow"])),
-                 f3(*m["light_dir"]), f3(*m["albedo"]), float(m["k_ambient"]), float(m["k_diffuse"]))
+                 f3(*m["light_dir"]), f3(*m["albedo"]), float(m["k_ambient"]), float(m["k_diffuse"]),
+                 SHADING_MODELS[m.get("shading", "lambert")], float(m.get("k_specular", 0.0)),
+                 float(m.get("shininess", 1.0)), float(m.get("k_reflect", 0.0)))
 
 
 def _ptr(t):
@@ -227,15 +232,18 @@ def make_object(ob):
 
 
 # ------------------------------------------------------------------- render
-def render_scene(scene, device="cuda", counters=False, out=None, workspace=None):
+def render_scene(scene, device="cuda", counters=False, out=None, workspace=None, trap=False):
     """Render a scene (camera, list of objects, march) in one launch; returns
-    the frame dict with an extra "object_id" plane (int32, -1 on a miss)."""
+    the frame dict with an extra "object_id" plane (int32, -1 on a miss) and,
+    with trap=True, the orbit-trap planes "trap" [4, P]."""
     L = lib()
     dev = _device(device)
     objs = scene["objects"]
     fr = out if out is not None else alloc_frame(scene, dev, counters)
     if "object_id" not in fr:
         fr["object_id"] = torch.empty(fr["depth"].numel(), device=dev, dtype=torch.int32)
+    if trap and "trap" not in fr:
+        fr["trap"] = torch.empty(4, fr["depth"].numel(), device=dev, dtype=torch.float32)
     n = len(objs)
     arr = (Object * max(n, 1))(*[make_object(o) for o in objs])
     nbytes = int(L.frt_scene_workspace_bytes(max(n, 1)))
@@ -245,7 +253,7 @@ def render_scene(scene, device="cuda", counters=False, out=None, workspace=None)
         workspace = ws[off:off + nbytes]
     cam, mc = make_camera(scene["camera"]), make_march(scene["march"])
     _check(L.frt_render_scene(ctypes.byref(cam), arr, n, ctypes.byref(mc), make_frame(fr), _ptr(fr["object_id"]),
-                              _ptr(workspace), workspace.numel(), _stream(dev)))
+                              _ptr(fr.get("trap")), _ptr(workspace), workspace.numel(), _stream(dev)))
     return fr
 
 

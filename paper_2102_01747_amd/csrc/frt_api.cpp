@@ -204,6 +204,16 @@ bool validate(const frt_camera* cam, const frt_fractal* fr, const frt_plane* pla
     if (mc->refine_iters < 0 || mc->refine_iters > 32) { why = "refine_iters must be in [0, 32]"; return false; }
     if (mc->shadow != 0 && mc->shadow != 1) { why = "shadow must be 0 or 1"; return false; }
     if (!(norm3(mc->light_dir) > 0.0)) { why = "light_dir is zero"; return false; }
+    if (mc->shading != FRT_SHADING_LAMBERT && mc->shading != FRT_SHADING_PHONG) {
+        why = "unknown shading model"; return false;
+    }
+    if (mc->shading == FRT_SHADING_PHONG) {
+        if (!(mc->k_specular >= 0.0f && mc->k_specular <= 1e30f)) {
+            why = "k_specular must be finite and >= 0"; return false;
+        }
+        if (!(mc->shininess >= 1.0f && mc->shininess <= 1e4f)) { why = "shininess must be in [1, 10000]"; return false; }
+        if (!(mc->k_reflect >= 0.0f && mc->k_reflect <= 1.0f)) { why = "k_reflect must be in [0, 1]"; return false; }
+    }
     if (need_outputs) {
         if (!out || !out->depth || !out->normal || !out->colour || !out->status) {
             why = "null output plane"; return false;
@@ -306,6 +316,10 @@ void pack(const frt_camera* cam, const frt_fractal* fr, const frt_plane* planes,
     }
     J.k_a = mc->k_ambient;
     J.k_d = mc->k_diffuse;
+    J.shading = mc->shading;
+    J.k_s = mc->k_specular;
+    J.shininess = mc->shininess;
+    J.k_r = mc->k_reflect;
     // outputs
     J.depth = out.depth;
     J.normal = out.normal;
@@ -427,8 +441,8 @@ size_t frt_scene_workspace_bytes(int32_t n_objects) {
 }
 
 frt_status frt_render_scene(const frt_camera* cam, const frt_object* objects, int32_t n_objects,
-                            const frt_march* march, frt_frame out, int32_t* object_id, void* workspace,
-                            size_t ws_bytes, void* stream) {
+                            const frt_march* march, frt_frame out, int32_t* object_id, float* trap,
+                            void* workspace, size_t ws_bytes, void* stream) {
     g_last_error.clear();
     if (!objects || n_objects < 1 || n_objects > frt::kMaxSceneObjects)
         return fail(FRT_EINVAL, "n_objects must be in [1, 16] with a non-null table");
@@ -486,7 +500,7 @@ frt_status frt_render_scene(const frt_camera* cam, const frt_object* objects, in
     frt_status s = upload_parts(parts, sizes, 2, workspace, st);
     if (s != FRT_OK) return s;
     const auto* objs = reinterpret_cast<const frt::SceneObject*>(static_cast<char*>(workspace) + sizeof(hdr));
-    hipError_t e = frt::launch_scene(objs, n_objects, camJ, object_id, st);
+    hipError_t e = frt::launch_scene(objs, n_objects, camJ, object_id, trap, st);
     if (e != hipSuccess) return hip_fail(e, "scene launch");
     return FRT_OK;
 }
@@ -496,6 +510,8 @@ frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_
     g_last_error.clear();
     std::string why;
     if (!validate(cam, frac, planes, n_planes, march, &out, true, why)) return fail(FRT_EINVAL, why);
+    if (march->shading != FRT_SHADING_LAMBERT)
+        return fail(FRT_EUNSUPPORTED, "the closest-hit shading model is rendered by frt_render_scene");
     frt_status s = check_workspace(workspace, ws_bytes, 1);
     if (s != FRT_OK) return s;
     JobDev J;
@@ -528,6 +544,9 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
         const frt_job& jb = jobs[i];
         if (!validate(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, &jb.out, true, why))
             return fail(FRT_EINVAL, "job " + std::to_string(i) + ": " + why);
+        if (jb.march.shading != FRT_SHADING_LAMBERT)
+            return fail(FRT_EUNSUPPORTED,
+                        "job " + std::to_string(i) + ": the closest-hit shading model is rendered by frt_render_scene");
         pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, 0, packed[size_t(i)]);
         var_of[size_t(i)] = variant_of(packed[size_t(i)]);
     }
@@ -702,6 +721,8 @@ frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float*
         const frt_job& jb = jobs[i];
         if (!validate(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, &jb.out, false, why))
             return fail(FRT_EINVAL, "job " + std::to_string(i) + ": " + why);
+        if (jb.march.shading != FRT_SHADING_LAMBERT)
+            return fail(FRT_EUNSUPPORTED, "job " + std::to_string(i) + ": the adjoint covers the Lambert model only");
         if (!jb.out.depth || !jb.out.status)
             return fail(FRT_EINVAL, "job " + std::to_string(i) + ": null depth or status plane");
         if (jb.march.normal_mode == FRT_NORMAL_ANALYTIC)

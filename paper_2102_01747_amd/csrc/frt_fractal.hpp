@@ -63,6 +63,10 @@ struct JuliaOrbit {
         prod = 1.0f;
         k = 0;
     }
+    // current orbit point (first three components) and |z|^2
+    __device__ __forceinline__ void point(float& x, float& y, float& z, float& m) const {
+        x = a; y = b; z = e; m = m2;
+    }
     __device__ __forceinline__ bool body(const OrbitParams& P) {
         prod *= m2;
         const float vv = fmaf(b, b, fmaf(e, e, w * w));
@@ -124,6 +128,10 @@ struct JuliaDegOrbit {
         m2 = fmaf(a, a, fmaf(b, b, e * e));
         dz2 = 1.0f;
         k = 0;
+    }
+    // current orbit point (first three components) and |z|^2
+    __device__ __forceinline__ void point(float& x, float& y, float& z, float& m) const {
+        x = a; y = b; z = e; m = m2;
     }
     // z^p + c into (na, nb, ne, nw) and the body's derivative factor
     __device__ __forceinline__ void map(const OrbitParams& P, float& na, float& nb, float& ne, float& nw,
@@ -199,6 +207,10 @@ struct BulbOrbit {
         m = fmaf(x, x, fmaf(y, y, z * z));
         dr = 1.0f;
         k = 0;
+    }
+    // current orbit point and |w|^2
+    __device__ __forceinline__ void point(float& x, float& y, float& z, float& mm) const {
+        x = wx; y = wy; z = wz; mm = m;
     }
     // one body from (w, m, dr): the new point and derivative
     __device__ __forceinline__ void map(const OrbitParams& P, float& nx, float& ny, float& nz, float& ndr) const {

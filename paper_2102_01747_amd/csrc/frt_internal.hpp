@@ -45,7 +45,8 @@ hipError_t launch_normal_query(int variant, const OrbitParams& P, int mode, cons
                                long long n, float* out, hipStream_t stream);
 // One view of a scene (frt_scene.hip): objs is the device table of n_obj
 // objects, cam the world camera, march and output planes.
-hipError_t launch_scene(const SceneObject* objs, int n_obj, const JobDev& cam, int* object_id, hipStream_t stream);
+hipError_t launch_scene(const SceneObject* objs, int n_obj, const JobDev& cam, int* object_id, float* trap,
+                        hipStream_t stream);
 hipError_t launch_math(int func, const float* x, const float* y, float* out, long long n, hipStream_t stream);
 
 // Adjoint over the hit pixels of a batch (frt_adjoint.hip): zeroes the

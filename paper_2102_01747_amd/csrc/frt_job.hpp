@@ -30,6 +30,7 @@ enum : uint8_t {
     kFlagShadowed = 8,
     kFlagUnrefined = 16,
     kFlagShadowRay = 64,   // set by the normal kernel on hits that cast a shadow ray
+    kFlagReflectHit = 128, // scenes with the closest-hit shading: the reflection ray hit
 };
 
 constexpr int kCounterPlanes = 8;      // optional per-pixel work counters
@@ -58,6 +59,8 @@ struct alignas(16) JobDev {
     float light[3];
     float albedo[3];
     float k_a, k_d;
+    int32_t shading;
+    float k_s, shininess, k_r;
     // outputs (SoA planes of npix)
     float* depth;
     float* normal;

@@ -71,6 +71,30 @@ __device__ __forceinline__ void estimate_normal(const OrbitParams& P, int mode, 
     }
 }
 
+// Orbit trap at a point: the minima of |x|, |y|, |z| and of the squared
+// norm over the start point and the result of every body of the estimate's
+// orbit (the colour parameters of the Mandelbulb distance listing).
+template <int VAR>
+__device__ __forceinline__ void orbit_trap(const OrbitParams& P, float x, float y, float z, float (&tr)[4]) {
+    typename OrbitOf<VAR>::T o;
+    o.init(x, y, z);
+    float px, py, pz, m;
+    o.point(px, py, pz, m);
+    tr[0] = fabsf(px);
+    tr[1] = fabsf(py);
+    tr[2] = fabsf(pz);
+    tr[3] = m;
+    while (o.k < P.max_iter) {
+        const bool in = o.body(P);
+        o.point(px, py, pz, m);
+        tr[0] = fminf(tr[0], fabsf(px));
+        tr[1] = fminf(tr[1], fabsf(py));
+        tr[2] = fminf(tr[2], fabsf(pz));
+        tr[3] = fminf(tr[3], m);
+        if (!in) break;
+    }
+}
+
 // Unit vector along (gx, gy, gz), scaled by the largest component first
 // (analytic gradients carry the orbit's derivative magnitude, whose square
 // may exceed float range).  Returns false for a zero or non-finite gradient.

@@ -16,7 +16,11 @@
 // capping an object's range at the best world depth so far plus one full
 // step, so a later object can only replace the hit with a closer one (ties
 // keep the lower index).  The hit is shaded in world space; its shadow ray
-// is blocked by a hit on any object.
+// is blocked by a hit on any object.  With the closest-hit shading model a
+// white Phong highlight is added, and one reflection ray, traced against
+// every object with the threshold carried on from eps(t*), adds its hit's
+// Lambert and highlight terms weighted by Schlick's Fresnel term
+// (f0 = albedo).  The orbit trap at the hit point is written on request.
 #include <hip/hip_runtime.h>
 
 #include "frt_internal.hpp"
@@ -143,6 +147,27 @@ __device__ void normal_any(int variant, const OrbitParams& P, int mode, float x,
     }
 }
 
+__device__ void trap_any(int variant, const OrbitParams& P, float x, float y, float z, float (&tr)[4]) {
+    switch (variant) {
+        case kVarJulia: orbit_trap<kVarJulia>(P, x, y, z, tr); break;
+        case kVarBulbReal: orbit_trap<kVarBulbReal>(P, x, y, z, tr); break;
+        case kVarBulbInt: orbit_trap<kVarBulbInt>(P, x, y, z, tr); break;
+        case kVarBulb8: orbit_trap<kVarBulb8>(P, x, y, z, tr); break;
+        default: orbit_trap<kVarJuliaDeg>(P, x, y, z, tr); break;
+    }
+}
+
+// Phong highlight max(0, R.V)^shininess, R = 2 (N.L) N - L; 0 when N.L <= 0
+__device__ __forceinline__ float phong_spec(float nx, float ny, float nz, const float* L, float vx, float vy, float vz,
+                                            float ndl, float shininess) {
+    if (!(ndl > 0.0f)) return 0.0f;
+    const float rx = fmaf(2.0f * ndl, nx, -L[0]);
+    const float ry = fmaf(2.0f * ndl, ny, -L[1]);
+    const float rz = fmaf(2.0f * ndl, nz, -L[2]);
+    const float rv = fmaf(rx, vx, fmaf(ry, vy, rz * vz));
+    return rv > 0.0f ? hw_exp2(shininess * hw_log2(rv)) : 0.0f;
+}
+
 // world point / direction -> object frame (x_obj = R^T (x - T) / s; directions R^T d)
 __device__ __forceinline__ void to_object(const SceneObject& S, float x, float y, float z, bool point, float& ox,
                                           float& oy, float& oz) {
@@ -168,7 +193,8 @@ __device__ __forceinline__ void to_object(const SceneObject& S, float x, float y
 }  // namespace
 
 __global__ void __launch_bounds__(256) scene_kernel(const SceneObject* __restrict__ objs, int n_obj,
-                                                    const JobDev cam, int* __restrict__ object_id) {
+                                                    const JobDev cam, int* __restrict__ object_id,
+                                                    float* __restrict__ trap) {
     const long long g = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     int j, px, py;
     if (!ray_pixel<false>(nullptr, cam, 1, g, j, px, py)) return;
@@ -216,6 +242,8 @@ __global__ void __launch_bounds__(256) scene_kernel(const SceneObject* __restric
         cam.status[p] = static_cast<uint8_t>(entered ? kMissTmax : kMissBounds);
         if (cam.counters)
             for (int c = 0; c < kCounterPlanes; ++c) cam.counters[c * NP + p] = 0u;
+        if (trap)
+            for (int c = 0; c < 4; ++c) trap[c * NP + p] = 0.0f;
         return;
     }
 
@@ -285,13 +313,103 @@ __global__ void __launch_bounds__(256) scene_kernel(const SceneObject* __restric
         }
     }
     const float lam = fmaf(cam.k_d * vis, fmaxf(ndl, 0.0f), cam.k_a);
+    float col[3] = {cam.albedo[0] * lam, cam.albedo[1] * lam, cam.albedo[2] * lam};
+    if (cam.shading == 1) {
+        // closest-hit shading: highlight, then one reflection bounce
+        const float spec = cam.k_s * vis * phong_spec(nx, ny, nz, cam.light, -dx, -dy, -dz, ndl, cam.shininess);
+        for (int c = 0; c < 3; ++c) col[c] += spec;
+        const float dn = fmaf(dx, nx, fmaf(dy, ny, dz * nz));
+        const float rdx = fmaf(-2.0f * dn, nx, dx), rdy = fmaf(-2.0f * dn, ny, dy), rdz = fmaf(-2.0f * dn, nz, dz);
+        const float eps_s = fmaf(cam.eps_rel, tw, cam.eps_abs);
+        const float off = 4.0f * eps_s;
+        const float qx = fmaf(off, nx, fmaf(tw, dx, ex));
+        const float qy = fmaf(off, ny, fmaf(tw, dy, ey));
+        const float qz = fmaf(off, nz, fmaf(tw, dz, ez));
+        int rbest = -1;
+        float rtw = 0.0f, rox = 0.f, roy = 0.f, roz = 0.f, rvx = 0.f, rvy = 0.f, rvz = 0.f, reo = 0.f;
+        MarchOut rh{kMissBounds, -1.0f, 0, 0, -1, 0u, 0u, false};
+        for (int k = 0; k < n_obj; ++k) {
+            const SceneObject& O = objs[k];
+            const JobDev& JO = O.job;
+            const OrbitParams P = orbit_params(JO);
+            float sox, soy, soz, sdx, sdy, sdz;
+            to_object(O, qx, qy, qz, true, sox, soy, soz);
+            to_object(O, rdx, rdy, rdz, false, sdx, sdy, sdz);
+            const float eo = eps_s * O.inv_scale;
+            const float cap = rbest >= 0 ? fmaf(rtw, O.inv_scale, JO.clamp) : JO.t_max;
+            const MarchOut r = march_any(O.variant, JO, P, sox, soy, soz, sdx, sdy, sdz, eo, cap, eo, JO.eps_rel, false);
+            sev += r.evals;
+            sbo += r.bodies;
+            if ((r.status & 7) >= kHit) {
+                const float t_w = r.t * O.scale;
+                if (rbest < 0 || t_w < rtw) {
+                    rbest = k;
+                    rtw = t_w;
+                    rh = r;
+                    rox = sox; roy = soy; roz = soz;
+                    rvx = sdx; rvy = sdy; rvz = sdz;
+                    reo = eo;
+                }
+            }
+        }
+        if (rbest >= 0) {
+            status |= kFlagReflectHit;
+            const SceneObject& O = objs[rbest];
+            const JobDev& JO = O.job;
+            float mx, my, mz;
+            if ((rh.status & 7) == kHitCut) {
+                mx = JO.pn[rh.entry][0];
+                my = JO.pn[rh.entry][1];
+                mz = JO.pn[rh.entry][2];
+            } else {
+                const OrbitParams P = orbit_params(JO);
+                float gx, gy, gz;
+                unsigned ev = 0, bo = 0;
+                normal_any(O.variant, P, JO.normal_mode, fmaf(rh.t, rvx, rox), fmaf(rh.t, rvy, roy),
+                           fmaf(rh.t, rvz, roz), fmaf(JO.eps_rel, rh.t, reo), gx, gy, gz, ev, bo);
+                sev += ev;
+                sbo += bo;
+                if (!unit_normal(gx, gy, gz, mx, my, mz)) {
+                    mx = -rvx;
+                    my = -rvy;
+                    mz = -rvz;
+                }
+            }
+            const float* RO = O.rot;
+            float wx = fmaf(RO[0], mx, fmaf(RO[1], my, RO[2] * mz));
+            float wy = fmaf(RO[3], mx, fmaf(RO[4], my, RO[5] * mz));
+            float wz = fmaf(RO[6], mx, fmaf(RO[7], my, RO[8] * mz));
+            float ux, uy, uz;
+            if (unit_normal(wx, wy, wz, ux, uy, uz)) {
+                wx = ux;
+                wy = uy;
+                wz = uz;
+            }
+            const float rndl = fmaf(wx, cam.light[0], fmaf(wy, cam.light[1], wz * cam.light[2]));
+            const float rlam = fmaf(cam.k_d, fmaxf(rndl, 0.0f), cam.k_a);
+            const float rspec = cam.k_s * phong_spec(wx, wy, wz, cam.light, -rdx, -rdy, -rdz, rndl, cam.shininess);
+            const float ci = 1.0f - fmaxf(0.0f, -dn);
+            const float ci2 = ci * ci;
+            const float f5 = ci2 * ci2 * ci;
+            for (int c = 0; c < 3; ++c) {
+                const float F = fmaf(1.0f - cam.albedo[c], f5, cam.albedo[c]);
+                col[c] = fmaf(cam.k_r * F, fmaf(cam.albedo[c], rlam, rspec), col[c]);
+            }
+        }
+    }
+    if (trap) {
+        const OrbitParams P = orbit_params(J);
+        float tr[4];
+        trap_any(S.variant, P, fmaf(hit.t, bdx, box), fmaf(hit.t, bdy, boy), fmaf(hit.t, bdz, boz), tr);
+        for (int c = 0; c < 4; ++c) trap[c * NP + p] = tr[c];
+    }
     cam.depth[p] = tw;
     cam.normal[p] = nx;
     cam.normal[NP + p] = ny;
     cam.normal[2 * NP + p] = nz;
-    cam.colour[p] = cam.albedo[0] * lam;
-    cam.colour[NP + p] = cam.albedo[1] * lam;
-    cam.colour[2 * NP + p] = cam.albedo[2] * lam;
+    cam.colour[p] = col[0];
+    cam.colour[NP + p] = col[1];
+    cam.colour[2 * NP + p] = col[2];
     cam.status[p] = static_cast<uint8_t>(status);
     if (cam.counters) {
         cam.counters[p] = static_cast<unsigned>(hit.steps);
@@ -305,12 +423,13 @@ __global__ void __launch_bounds__(256) scene_kernel(const SceneObject* __restric
     }
 }
 
-hipError_t launch_scene(const SceneObject* objs, int n_obj, const JobDev& cam, int* object_id, hipStream_t stream) {
+hipError_t launch_scene(const SceneObject* objs, int n_obj, const JobDev& cam, int* object_id, float* trap,
+                        hipStream_t stream) {
     const long long rays = cam.ray_count;
     const int block = 256;
     const long long grid = (rays + block - 1) / block;
     hipLaunchKernelGGL(scene_kernel, dim3(static_cast<unsigned>(grid)), dim3(block), 0, stream, objs, n_obj, cam,
-                       object_id);
+                       object_id, trap);
     return hipGetLastError();
 }
 

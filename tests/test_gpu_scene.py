@@ -146,3 +146,78 @@ def test_scene_rejects_bad_arguments(frt):
             frt.render_scene(s_, "cuda", out=fr)
     torch.cuda.synchronize()
     assert torch.all(fr["depth"] == 7.0)
+
+
+# ------------------------------------------------ closest-hit shading (R23)
+def _ball(translation, scale):
+    return W.scene_object(W.julia([0, 0, 0, 0], 11, bound_radius=1.5), translation=translation, scale=scale)
+
+
+def _shaded_parity(frt, orc, sc, **kw):
+    fr = frt.render_scene(sc, "cuda", counters=True, trap=True)
+    torch.cuda.synchronize()
+    g = to_numpy(fr)
+    o = orc.render_scene(sc)
+    cam = sc["camera"]
+    H, W_ = cam["height"], cam["width"]
+    nd = id_neighbour_flags(o["object_id"].reshape(H, W_), o["status"].reshape(H, W_)).ravel()
+    st = compare_scene(orc, sc, g, o, nd)
+    print(st, flush=True)
+    assert_scene_parity(st, **kw)
+    return g, o
+
+
+def test_two_ball_reflections(frt, orc):
+    """Two c = 0 balls with the closest-hit shading: Phong highlights and
+    reflections of one ball in the other (closed form in the oracle pins)."""
+    mc = W.phong(W.march(256, eps_abs=1e-3, t_max=20.0, normal_mode="analytic", shadow=True))
+    sc = W.scene(W.camera((0.0, 0.3, 3.0), 192, 144), [_ball((-0.7, 0.0, 0.0), 0.6), _ball((0.75, 0.1, -0.3), 0.5)],
+                 mc)
+    g, o = _shaded_parity(frt, orc, sc)
+    assert np.sum((g["status"] & 128) != 0) > 100
+
+
+@pytest.mark.parametrize("mode", ["tetra", "analytic"])
+def test_overlap_scene_closest_hit_shading_and_trap(frt, orc, mode):
+    sc = W.overlap_scene(width=200, height=150, normal_mode=mode)
+    sc["march"] = W.phong(sc["march"])
+    g, o = _shaded_parity(frt, orc, sc, colour_ok=0.99)
+    assert np.sum((g["status"] & 128) != 0) > 200
+    # orbit trap at the GPU's own hit point, in the object's frame
+    hit = np.nonzero(g["object_id"] >= 0)[0]
+    orig, dirs = orc.camera_rays(sc["camera"], hit)
+    # Hit points lie within eps of the set, where the orbit amplifies
+    # rounding.  A trap is well conditioned when perturbing every power by
+    # the float32 rounding budget (relative 2 p 2^-24, the normals' probe)
+    # moves the FP64 trap by less than 1e-4 over four seeds, and no body
+    # comes within 1e-4 of the bailout; there the GPU's trap must agree to
+    # 1e-3 (absolute: the trap holds orbit coordinates of size ~1).
+    ref = np.zeros((4, hit.size))
+    ill = np.zeros(hit.size, bool)
+    for k, ob in enumerate(sc["objects"]):
+        m = g["object_id"][hit] == k
+        R, T, s = orc.object_frame(ob)
+        p = (orig[m] + g["depth"][hit][m, None].astype(np.float64) * dirs[m] - T) @ R / s
+        ref[:, m] = orc.orbit_trap(ob["fractal"], p).T
+        rel = 2.0 * ob["fractal"]["power"] * 2.0 ** -24
+        for seed in range(4):
+            alt = orc.orbit_trap_perturbed(ob["fractal"], p, rel, 2000 + seed).T
+            ill[m] |= np.any(np.abs(alt - ref[:, m]) > 1e-4, axis=0)
+        mg, _ = orc.escape_margin(ob["fractal"], p)
+        ill[m] |= mg < 1e-4
+    err = np.abs(g["trap"][:, hit] - ref).max(0)
+    ok = err[~ill] <= 1e-3
+    print("trap: well conditioned %.4f, agreement there %.5f; abs error p50 %.2e, p99 (all) %.2e"
+          % ((~ill).mean(), ok.mean(), np.median(err), np.percentile(err, 99)))
+    assert (~ill).mean() > 0.8
+    assert ok.mean() > 0.999
+    assert np.all(g["trap"][:, g["object_id"] < 0] == 0.0)
+
+
+def test_single_renderers_refuse_the_closest_hit_shading(frt):
+    job = W.julia_view(width=16, height=16)
+    job["march"] = W.phong(job["march"])
+    with pytest.raises(frt.FrtError, match="unsupported"):
+        frt.render(job, "cuda")
+    with pytest.raises(frt.FrtError, match="unsupported"):
+        frt.render_batch([job], "cuda")
