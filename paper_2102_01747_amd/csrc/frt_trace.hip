@@ -476,8 +476,10 @@ static hipError_t launch_stage(int stage, const LaunchCfg& cfg, const JobDev* jo
         hipLaunchKernelGGL((normal_kernel<VAR, BATCH>), dim3(cfg.normal_grid), dim3(256), 0, stream, jobs, job1,
                            hdr);
     } else {
+        // a tile holds few shadow rays (only lit hits cast one), so a claim
+        // covers twice the primary march's rays to keep the queue traffic down
         hipLaunchKernelGGL((march_kernel<VAR, BATCH, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, jobs,
-                           job1, hdr, cfg.chunk, cfg.orbit_lanes, cfg.rare_lanes);
+                           job1, hdr, 2 * cfg.chunk, cfg.orbit_lanes, cfg.rare_lanes);
     }
     return hipGetLastError();
 }
