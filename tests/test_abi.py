@@ -54,6 +54,9 @@ def test_host_only_calls_without_gpu():
     assert L.frt_render_batch(None, 0, None, 0, 0, None) == frt.FRT_EINVAL
     sa, sb = int(L.frt_scene_workspace_bytes(1)), int(L.frt_scene_workspace_bytes(16))
     assert sa % 256 == 0 and sb % 256 == 0 and sb > sa > 1024
+    # scene validation happens before anything touches a device
+    assert L.frt_render_scene(None, None, 0, None, frt.Frame(), None, None, None, 0, None) == frt.FRT_EINVAL
+    assert b"n_objects" in L.frt_last_error()
 
 
 def test_ctypes_layout_matches_c_header(tmp_path):

@@ -221,3 +221,44 @@ def test_single_renderers_refuse_the_closest_hit_shading(frt):
         frt.render(job, "cuda")
     with pytest.raises(frt.FrtError, match="unsupported"):
         frt.render_batch([job], "cuda")
+
+
+def test_sixteen_object_scene(frt, orc):
+    """The largest scene: a 4 x 4 grid of small objects of every kernel
+    variant (Julia of degree 2 and 3, Mandelbulb with n = 8, 5 and 6.37),
+    each with its own rotation and scale, with shadows."""
+    kinds = [W.julia(W.JULIA_C1, 9), W.julia(W.JULIA_C3, 8, degree=3), W.bulb(8.0, 8), W.bulb(5.0, 8),
+             W.bulb(6.37, 8)]
+    objs = []
+    for k in range(16):
+        gx, gy = k % 4, k // 4
+        objs.append(W.scene_object(kinds[k % len(kinds)], rot=W.rotation([1.0, 0.3 * k, 0.2], 0.4 * k),
+                                   translation=(-1.5 + gx, -1.5 + gy, 0.1 * (k % 3)), scale=0.4 + 0.02 * k))
+    sc = W.scene(W.camera((0.0, 0.2, 5.0), 160, 120), objs,
+                 W.march(512, eps_rel=5e-4, shadow=True, normal_mode="central", t_max=20.0))
+    fr = frt.render_scene(sc, "cuda", counters=True)
+    torch.cuda.synchronize()
+    g = to_numpy(fr)
+    o = orc.render_scene(sc)
+    nd = id_neighbour_flags(o["object_id"].reshape(120, 160), o["status"].reshape(120, 160)).ravel()
+    st = compare_scene(orc, sc, g, o, nd)
+    print(st)
+    assert len(set(o["object_id"][o["object_id"] >= 0].tolist())) == 16
+    assert_scene_parity(st)
+
+
+def test_scene_workspace_too_small(frt):
+    sc = W.julia_bulb_scene(width=16, height=16)
+    small = torch.empty(1024, device="cuda", dtype=torch.uint8)
+    with pytest.raises(frt.FrtError, match="workspace too small"):
+        frt.render_scene(sc, "cuda", workspace=small)
+
+
+def test_normal_query_rejects_bad_arguments(frt):
+    fr = W.julia(W.JULIA_C1, 11)
+    pts = torch.zeros(4, 3, device="cuda")
+    with pytest.raises(frt.FrtError, match="need eps"):
+        frt.normal_at(fr, pts, "tetra")
+    with pytest.raises(frt.FrtError, match="normal_mode"):
+        frt.normal_at(fr, pts, 7, eps=torch.ones(4, device="cuda"))
+    assert frt.normal_at(fr, torch.zeros(0, 3, device="cuda"), "analytic").shape == (0, 3)
