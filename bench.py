@@ -161,6 +161,17 @@ def adjoint_leg(frt, dev, reps):
             "rel_err_target": 1e-3}
 
 
+def measured_ceilings(frt, dev, achieved):
+    """Sustained FP32 FMA and transcendental issue rates of this device under
+    the build's code generation (packed FP32 off), from the library's rate
+    probes; the dominant kernel's algorithmic rate as a fraction of the
+    measured FMA ceiling."""
+    fma = frt.valu_rate("fma", 16384, dev) * 2 / 1e12          # TFLOP/s, FMA = 2
+    trans = {op: frt.valu_rate(op, 4096, dev) / 1e12 for op in ("exp2", "log2", "rsq", "sin_rev")}
+    return {"measured_fma_tflops": fma, "frac_of_measured_fma": achieved / fma,
+            "measured_trans_tops": trans}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +181,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the vector-unit rate probes")
     ap.add_argument("--tune", action="store_true",
                     help="re-run the autotuner on this workload before timing (default: the recorded tuned.json)")
     ap.add_argument("--workload", choices=["bulb_views", "stress"], default="bulb_views",
@@ -308,6 +320,8 @@ def main():
         "whole_path_tflops": float(flops.sum() / (ms_step * 1e-3) / 1e12),
         "launch_config": launch_cfg,
     }
+    if not args.no_ceilings:
+        rec["roofline"].update(measured_ceilings(frt, dev, achieved))
     if not args.no_adjoint and args.workload == "bulb_views":
         rec["adjoint"] = adjoint_leg(frt, dev, max(3, args.steps // 4))
     if not args.no_cpu_baseline and args.workload == "bulb_views":

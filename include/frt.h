@@ -309,6 +309,21 @@ frt_status frt_normal_at(const frt_fractal* frac, int32_t normal_mode, const flo
  * y is read only by func 1.                                                 */
 frt_status frt_math_eval(int32_t func, const float* x, const float* y, float* out, int64_t n, void* stream);
 
+/* Measurement utility, not a step of the method: the sustained device-wide
+ * issue rate of one FP32 vector operation, for the ceilings the march
+ * kernels are measured against (the kernels are bound by the vector unit).
+ * op: 0 FMA, 1 exp2, 2 log2, 3 1/sqrt, 4 1/x, 5 sqrt, 6 sin(2 pi x),
+ * 7 a mix of four dependent FMAs per exp2 (whether transcendentals overlap
+ * FMAs).  Each lane of 8 workgroups of 256 threads per compute unit runs
+ * eight independent chains for iters rounds, iters in [1, 1 << 20]; op 7
+ * counts five operations per chain and round.  *lane_ops_per_s receives
+ * the lane operations per second of one timed launch (after one untimed
+ * launch); an FMA is one operation (two FLOP).  Allocates and frees a
+ * device buffer of 1 KiB per workgroup and waits for the launches on
+ * stream.  FRT_EINVAL for an unknown op, iters out of range or a null
+ * output; FRT_EHIP for a failed HIP call.                                   */
+frt_status frt_valu_rate(int32_t op, int32_t iters, double* lane_ops_per_s, void* stream);
+
 /* Launch configuration of the persistent kernels, chosen by the autotuner.
  * kernel_variant: 0 Julia z^2 + c, 1 Mandelbulb (real n), 2 Mandelbulb
  * (integer n), 3 Mandelbulb with n = 8 (the power the paper renders),

@@ -106,6 +106,8 @@ def lib():
         L.frt_normal_at.restype = ctypes.c_int
         L.frt_math_eval.argtypes = [i32, vp, vp, vp, ctypes.c_int64, vp]
         L.frt_math_eval.restype = ctypes.c_int
+        L.frt_valu_rate.argtypes = [i32, i32, P(ctypes.c_double), vp]
+        L.frt_valu_rate.restype = ctypes.c_int
         L.frt_set_stage_timing.argtypes = [i32]
         L.frt_set_stage_timing.restype = ctypes.c_int
         L.frt_stage_times.argtypes = [P(ctypes.c_float)]
@@ -372,6 +374,18 @@ def math_eval(func, x, y=None, device="cuda"):
     out = torch.empty_like(xs)
     _check(lib().frt_math_eval(MATH_FUNCS[func], _ptr(xs), _ptr(ys), _ptr(out), xs.numel(), _stream(dev)))
     return out
+
+
+RATE_OPS = {"fma": 0, "exp2": 1, "log2": 2, "rsq": 3, "rcp": 4, "sqrt": 5, "sin_rev": 6, "fma4_exp2": 7}
+
+
+def valu_rate(op, iters, device="cuda"):
+    """Sustained device-wide rate, in lane operations per second, of the FP32
+    vector operation `op` (see RATE_OPS; an FMA counts once)."""
+    dev = _device(device)
+    r = ctypes.c_double(0.0)
+    _check(lib().frt_valu_rate(RATE_OPS[op], int(iters), ctypes.byref(r), _stream(dev)))
+    return r.value
 
 
 def autotune_set(variant, block, chunk, waves_per_simd=0, orbit_lanes=8, rare_lanes=16):

@@ -703,6 +703,44 @@ frt_status frt_math_eval(int32_t func, const float* x, const float* y, float* ou
     return FRT_OK;
 }
 
+frt_status frt_valu_rate(int32_t op, int32_t iters, double* lane_ops_per_s, void* stream) {
+    g_last_error.clear();
+    if (op < 0 || op >= frt::kNumRateOps) return fail(FRT_EINVAL, "op must be in [0, 7]");
+    if (iters < 1 || iters > (1 << 20)) return fail(FRT_EINVAL, "iters must be in [1, 1 << 20]");
+    if (!lane_ops_per_s) return fail(FRT_EINVAL, "null output");
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    // 8 workgroups of 4 waves per CU: 8 waves on each of its 4 SIMDs
+    const int blocks = 8 * cus;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    float* sink = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    float ms = 0.0f;
+    e = hipMalloc(&sink, size_t(blocks) * frt::kRateBlock * sizeof(float));
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e == hipSuccess) e = frt::launch_rate(op, iters, sink, blocks, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) e = frt::launch_rate(op, iters, sink, blocks, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    const hipError_t first = e;
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (sink) {
+        const hipError_t ef = hipFree(sink);
+        if (e == hipSuccess) e = ef;
+    }
+    if (first != hipSuccess || e != hipSuccess) return hip_fail(first != hipSuccess ? first : e, "rate probe");
+    if (!(ms > 0.0f)) return fail(FRT_EHIP, "rate probe: zero elapsed time");
+    const double ops = double(blocks) * frt::kRateBlock * double(iters) * frt::rate_ops_per_iter(op);
+    *lane_ops_per_s = ops / (double(ms) * 1e-3);
+    return FRT_OK;
+}
+
 frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float* const* g_colour,
                                const float* const* g_depth, const float* const* g_normal,
                                float* const* grad_pixel, float* grad_c,

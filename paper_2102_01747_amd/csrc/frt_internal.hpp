@@ -49,6 +49,14 @@ hipError_t launch_scene(const SceneObject* objs, int n_obj, const JobDev& cam, i
                         hipStream_t stream);
 hipError_t launch_math(int func, const float* x, const float* y, float* out, long long n, hipStream_t stream);
 
+// Issue-rate probes of the vector unit (frt_rates.hip): `blocks` workgroups
+// of kRateBlock threads, each lane running `iters` rounds of
+// rate_ops_per_iter(op) lane operations; sink holds one float per thread.
+enum RateOp { kRateFma = 0, kRateExp2, kRateLog2, kRateRsq, kRateRcp, kRateSqrt, kRateSin, kRateMix, kNumRateOps };
+constexpr int kRateBlock = 256;
+int rate_ops_per_iter(int op);
+hipError_t launch_rate(int op, int iters, float* sink, int blocks, hipStream_t stream);
+
 // Adjoint over the hit pixels of a batch (frt_adjoint.hip): zeroes the
 // gradient outputs and the tile counters, then one persistent launch per
 // fractal kind present (grid[kind] workgroups of 256 threads, 0 = none)
