@@ -95,7 +95,7 @@ struct JuliaOrbit {
         prod = live ? pn : prod;
         m2 = live ? mn : m2;
         k = live ? kn : k;
-        return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2) && kn < P.max_iter);
+        return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2)) & __builtin_amdgcn_ballot_w64(kn < P.max_iter);
     }
     __device__ __forceinline__ DEResult result(const OrbitParams& P) const {
         DEResult r;
@@ -170,7 +170,7 @@ struct JuliaDegOrbit {
         dz2 = live ? dn : dz2;
         m2 = live ? mn : m2;
         k = live ? kn : k;
-        return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2) && kn < P.max_iter);
+        return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2)) & __builtin_amdgcn_ballot_w64(kn < P.max_iter);
     }
     __device__ __forceinline__ DEResult result(const OrbitParams& P) const {
         DEResult r;
@@ -196,6 +196,15 @@ struct JuliaDegOrbit {
 //   axis (rho = 0) the azimuth factor is 1, matching atan2(0, 0) = 0.
 // r = 0 maps to w = p, dr = 1 in every mode.
 // ---------------------------------------------------------------------------
+// r^(K-1) from m = r^2 for a compile-time integer power K >= 2: m^((K-1)/2)
+// for odd K, m^(K/2-1) sqrt(m) for even K (sqrt(0) = 0 needs no floor).
+template <int K>
+__device__ __forceinline__ float bulb_rpow(float m) {
+    if constexpr (K & 1) return ipow_c<(K - 1) / 2>(m);
+    else if constexpr (K == 2) return hw_sqrt(m);
+    else return ipow_c<K / 2 - 1>(m) * hw_sqrt(m);
+}
+
 template <int MODE>
 struct BulbOrbit {
     float wx, wy, wz, m, dr, px, py, pz;
@@ -233,18 +242,11 @@ struct BulbOrbit {
             float yr = wy, yi = rho2 * irho;
             float zr = wz * irho, zi = wx * irho;
             if constexpr (MODE > 0) {
-                if constexpr ((MODE & 1) == 0) {
-                    const float rinv = hw_rsq(fmaxf(m, kTinyFloor));
-                    ndr = fmaf(static_cast<float>(MODE) * (ipow_c<MODE / 2>(m) * rinv), dr, 1.0f);
-                } else {
-                    ndr = fmaf(static_cast<float>(MODE) * ipow_c<(MODE - 1) / 2>(m), dr, 1.0f);
-                }
+                ndr = fmaf(static_cast<float>(MODE) * bulb_rpow<MODE>(m), dr, 1.0f);
                 cpow_c<MODE>(yr, yi);
                 cpow_c<MODE>(zr, zi);
             } else {
-                const float rinv = hw_rsq(fmaxf(m, kTinyFloor));
-                const float r = m * rinv;
-                ndr = fmaf(P.n * ipow(r, P.ipow - 1), dr, 1.0f);
+                ndr = fmaf(P.n * ipow(hw_sqrt(m), P.ipow - 1), dr, 1.0f);
                 cpow_int(yr, yi, P.ipow);
                 cpow_int(zr, zi, P.ipow);
             }
@@ -263,7 +265,7 @@ struct BulbOrbit {
         dr = live ? ndr : dr;
         m = live ? mn : m;
         k = live ? kn : k;
-        return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2) && kn < P.max_iter);
+        return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2)) & __builtin_amdgcn_ballot_w64(kn < P.max_iter);
     }
     __device__ __forceinline__ bool body(const OrbitParams& P) {
         if constexpr (MODE == 0) {
@@ -289,19 +291,11 @@ struct BulbOrbit {
             float yr = wy, yi = rho2 * irho;
             float zr = wz * irho, zi = wx * irho;
             if constexpr (MODE > 0) {
-                // r^(n-1) = m^(n/2) / r for even n, m^((n-1)/2) for odd n
-                if constexpr ((MODE & 1) == 0) {
-                    const float rinv = hw_rsq(fmaxf(m, kTinyFloor));
-                    dr = fmaf(static_cast<float>(MODE) * (ipow_c<MODE / 2>(m) * rinv), dr, 1.0f);
-                } else {
-                    dr = fmaf(static_cast<float>(MODE) * ipow_c<(MODE - 1) / 2>(m), dr, 1.0f);
-                }
+                dr = fmaf(static_cast<float>(MODE) * bulb_rpow<MODE>(m), dr, 1.0f);
                 cpow_c<MODE>(yr, yi);
                 cpow_c<MODE>(zr, zi);
             } else {
-                const float rinv = hw_rsq(fmaxf(m, kTinyFloor));
-                const float r = m * rinv;
-                dr = fmaf(P.n * ipow(r, P.ipow - 1), dr, 1.0f);
+                dr = fmaf(P.n * ipow(hw_sqrt(m), P.ipow - 1), dr, 1.0f);
                 cpow_int(yr, yi, P.ipow);
                 cpow_int(zr, zi, P.ipow);
             }
