@@ -101,6 +101,47 @@ __device__ __forceinline__ const JobDev& job_ref(const JobDev* __restrict__ jobs
     if constexpr (BATCH) return jobs[j]; else return job1;
 }
 
+// Pixel of ray r of a job (r counted from the job's first ray; 64 rays per
+// 8 x 8 pixel tile, tiles in row-major order); false for the padding lanes
+// of edge tiles.
+__device__ __forceinline__ bool tile_pixel(const JobDev& J, long long r, int& px, int& py) {
+    const int tile = static_cast<int>(r >> 6), wl = static_cast<int>(r & 63);
+    const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
+    px = tx * kTile + (wl & (kTile - 1));
+    py = ty * kTile + (wl >> 3);
+    return px < J.width && py < J.height;
+}
+
+// Wave-uniform cursor over the job table: the job whose ray range holds the
+// wave's current claim.  Every job's range is a whole number of 64-ray
+// tiles, so a tile never spans two jobs, and consecutive claims of a wave
+// need no search of the table and read the job through scalar loads.
+struct JobCursor {
+    int j = 0;
+    unsigned long long begin = 0, end = 0;
+};
+
+// Point the cursor at the job holding ray g (g must be wave-uniform).
+template <bool BATCH>
+__device__ __forceinline__ void job_seek(const JobDev* __restrict__ jobs, const JobDev& job1, int n_jobs,
+                                         unsigned long long g, JobCursor& c) {
+    if (g >= c.begin && g < c.end) return;
+    if constexpr (BATCH) {
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (static_cast<unsigned long long>(jobs[mid].ray_begin) <= g) lo = mid; else hi = mid - 1;
+        }
+        c.j = __builtin_amdgcn_readfirstlane(lo);
+        c.begin = static_cast<unsigned long long>(jobs[c.j].ray_begin);
+        c.end = c.begin + static_cast<unsigned long long>(jobs[c.j].ray_count);
+    } else {
+        c.j = 0;
+        c.begin = static_cast<unsigned long long>(job1.ray_begin);
+        c.end = c.begin + static_cast<unsigned long long>(job1.ray_count);
+    }
+}
+
 // Map a ray index of the batch to (job, pixel); false for the padding lanes
 // of edge tiles.
 template <bool BATCH>
@@ -116,12 +157,7 @@ __device__ __forceinline__ bool ray_pixel(const JobDev* __restrict__ jobs, const
         j = lo;
     }
     const JobDev& J = job_ref<BATCH>(jobs, job1, j);
-    const long long r = g - J.ray_begin;
-    const int tile = static_cast<int>(r >> 6), wl = static_cast<int>(r & 63);
-    const int ty = tile / J.tiles_x, tx = tile - ty * J.tiles_x;
-    px = tx * kTile + (wl & (kTile - 1));
-    py = ty * kTile + (wl >> 3);
-    return px < J.width && py < J.height;
+    return tile_pixel(J, g - J.ray_begin, px, py);
 }
 
 }  // namespace frt

@@ -64,6 +64,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
     }
     unsigned long long q_next = 0, q_end = 0;   // wave-uniform window of claimed rays
     bool drained = false;
+    JobCursor cur;                               // job of the current claim (wave-uniform)
     // shadow rays: the current tile's first ray index and the mask of its
     // shadow-casting pixels not yet handed to a lane (wave-uniform)
     unsigned long long tile_g = 0, tmask = 0;
@@ -152,12 +153,15 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                     q_next = base;
                     q_end = min(base + static_cast<unsigned long long>(chunk), r_end);
                 }
+                // this round's rays all lie in the cursor's job
+                job_seek<BATCH>(jobs, job1, n_jobs, q_next, cur);
                 const unsigned rank = lane_rank(idle);
-                const unsigned long long avail = q_end - q_next;
-                int j, px, py;
+                const unsigned long long avail = min(q_end, cur.end) - q_next;
+                const int j = cur.j;
+                const JobDev& J = job_ref<BATCH>(jobs, job1, j);
+                int px, py;
                 if (phase == kIdle && rank < avail &&
-                    ray_pixel<BATCH>(jobs, job1, n_jobs, static_cast<long long>(q_next + rank), j, px, py)) {
-                    const JobDev& J = job_ref<BATCH>(jobs, job1, j);
+                    tile_pixel(J, static_cast<long long>(q_next + rank - cur.begin), px, py)) {
                     const int p = py * J.width + px;
                     float lo, hi;
                     bool go = false;
@@ -228,13 +232,12 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                     }
                     tile_g = q_next;
                     q_next += 64ull;
-                    int j, px, py;
+                    job_seek<BATCH>(jobs, job1, n_jobs, tile_g, cur);
+                    const JobDev& J = job_ref<BATCH>(jobs, job1, cur.j);
+                    int px, py;
                     bool cast = false;
-                    if (ray_pixel<BATCH>(jobs, job1, n_jobs, static_cast<long long>(tile_g + __lane_id()), j, px,
-                                         py)) {
-                        const JobDev& J = job_ref<BATCH>(jobs, job1, j);
+                    if (tile_pixel(J, static_cast<long long>(tile_g - cur.begin) + __lane_id(), px, py))
                         cast = (J.status[py * J.width + px] & kFlagShadowRay) != 0;
-                    }
                     tmask = __ballot(cast);
                     continue;
                 }
@@ -245,9 +248,11 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                 const unsigned nidle = static_cast<unsigned>(__popcll(idle));
                 const unsigned rank = lane_rank(idle);
                 if (phase == kIdle && rank < nbits) {
-                    int j, px, py;
-                    ray_pixel<BATCH>(jobs, job1, n_jobs, static_cast<long long>(tile_g + slot[rank]), j, px, py);
+                    // the tile's job is the cursor's
+                    const int j = cur.j;
                     const JobDev& J = job_ref<BATCH>(jobs, job1, j);
+                    int px, py;
+                    tile_pixel(J, static_cast<long long>(tile_g - cur.begin) + slot[rank], px, py);
                     const int p = py * J.width + px;
                     const long long NP = J.npix;
                     const float nx = J.normal[p], ny = J.normal[NP + p], nz = J.normal[2 * NP + p];
@@ -411,11 +416,15 @@ __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ 
         r_end = hdr->range[VAR][1];
     }
     const unsigned long long stride = static_cast<unsigned long long>(gridDim.x) * blockDim.x;
+    JobCursor cur;
     for (unsigned long long g = r_begin + static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
          g < r_end; g += stride) {
-        int j, px, py;
-        if (!ray_pixel<BATCH>(jobs, job1, n_jobs, static_cast<long long>(g), j, px, py)) continue;
+        // a wave covers one 64-ray tile, inside one job
+        job_seek<BATCH>(jobs, job1, n_jobs, bcast_first(g - __lane_id()), cur);
+        const int j = cur.j;
         const JobDev& J = job_ref<BATCH>(jobs, job1, j);
+        int px, py;
+        if (!tile_pixel(J, static_cast<long long>(g - cur.begin), px, py)) continue;
         const int p = py * J.width + px;
         const int cls = J.status[p] & 7;
         if (cls < kHit) continue;
