@@ -110,6 +110,41 @@ def test_mixed_kind_batch(frt, orc):
         assert_parity(st)
 
 
+def _tiny_jobs():
+    """27 small renders (1x1 to 17x13) over all five kernel variants, some
+    with shadows and cut planes: several jobs fall inside one queue claim,
+    and job ranges end inside claims and tile groups."""
+    sizes = [(1, 1), (7, 5), (9, 9), (17, 3), (8, 8), (3, 17), (16, 9), (5, 13), (17, 13)]
+    jobs = []
+    for k, (w, h) in enumerate(sizes):
+        shadow = k % 2 == 0
+        planes = [W.plane([0.2, 1.0, 0.3], 0.05)] if k % 3 == 1 else []
+        jobs.append(W.julia_view(width=w, height=h, shadow=shadow, planes=planes))
+        jobs.append(W.bulb_view(0.3 + 0.5 * k, 0.2, width=h, height=w, shadow=not shadow, planes=planes,
+                                power=[8.0, 5.0, 6.37][k % 3]))
+        jobs.append(W.julia_view(c=W.JULIA_C3, degree=3, width=w + 2, height=h, shadow=shadow, planes=planes))
+    return jobs
+
+
+def test_tiny_jobs_share_claims(frt, orc):
+    jobs = _tiny_jobs()
+    outs = frt.render_batch(jobs, "cuda", counters=True)
+    singles = [frt.render(j, "cuda", counters=True) for j in jobs]
+    torch.cuda.synchronize()
+    hits = 0
+    for k, (job, fr, one) in enumerate(zip(jobs, outs, singles)):
+        g, s = to_numpy(fr), to_numpy(one)
+        assert _same(g, s) == 1.0, k
+        o = orc.render(job)
+        cam = job["camera"]
+        nd = neighbour_flags(o["status"].reshape(cam["height"], cam["width"])).ravel()
+        st = compare(orc, job, g, o, nd)
+        hits += st["oracle_hits"]
+        assert_parity(st)
+    print("tiny jobs: %d, oracle hits %d" % (len(jobs), hits))
+    assert hits > 200
+
+
 def test_batch_speedup_over_one_by_one(frt, batch_jobs):
     """Reports the throughput gain of one batched launch (and its graph
     replay) over the same 64 renders launched one by one."""
