@@ -43,6 +43,12 @@
  *       at the hit point itself, by forward-mode differentiation.
  *   R11 Lambert shading with one optional shadow ray replaces the paper's
  *       Phong/Fresnel closest-hit shader.
+ *
+ * Pins: the test suite ties every function here to closed forms, symmetries,
+ * special cases or brute force, except two rounding probes, which perturb
+ * each orbit body on purpose and only decide where the comparison tolerates
+ * rounding: oracle_normal_perturbed and oracle_trap_perturbed are parity
+ * unpinned.
  */
 #include <math.h>
 #include <stdint.h>

@@ -4,6 +4,10 @@ TEST INFRASTRUCTURE ONLY: the tests, the package smoke check and the
 benchmark's CPU-baseline leg use this module; the GPU library never does.
 It accepts the plain job dictionaries produced by ``workloads.py`` (float32
 values) and widens every parameter to double.
+
+The rounding probes ``normal_perturbed`` and ``orbit_trap_perturbed`` perturb
+every orbit body on purpose and only decide where a comparison tolerates
+rounding: parity unpinned.  Every other function is pinned by the tests.
 """
 import ctypes
 import os

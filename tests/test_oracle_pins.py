@@ -591,3 +591,45 @@ def test_analytic_normal_jacobian_is_not_provided(orc):
     jb = W.julia_view(width=8, height=8, normal_mode="analytic")
     with pytest.raises(NotImplementedError):
         orc.pixel_jacobian(jb, np.arange(64))
+
+
+@pytest.mark.parametrize("degree", [2, 3, 5])
+def test_escape_margin_julia_c0_closed_form(orc, degree):
+    """With c = 0 the orbit of x is x^(p^k), so |z_k|^2 = |x|^(2 p^k): the
+    margin is the smallest |m_k - B| / B up to the first m_k > B."""
+    fr = W.julia([0, 0, 0, 0], max_iter=9, bailout2=256.0, degree=degree)
+    rng = np.random.default_rng(5)
+    pts = rng.normal(size=(200, 3)) * rng.uniform(0.5, 1.6, size=(200, 1))
+    margin, esc = orc.escape_margin(fr, pts)
+    for p, mg, e in zip(pts, margin, esc):
+        m0, B = float(p @ p), 256.0
+        best, escaped = np.inf, False
+        for k in range(1, 10):
+            mk = m0 ** (degree ** k)
+            best = min(best, abs(mk - B) / B)
+            if mk > B:
+                escaped = True
+                break
+        assert e == escaped
+        assert mg == pytest.approx(best, rel=1e-9, abs=1e-12)
+
+
+def test_escape_margin_bulb_polar_axis(orc):
+    """On the polar (y) axis the n = 8 Mandelbulb map sends (0, y, 0) to
+    (0, |y|^8, 0) (theta is 0 or pi, and 8 theta a multiple of 2 pi), so the
+    orbit follows the 1-D recurrence y <- |y|^8 + y0."""
+    fr = W.bulb(8.0, 10)
+    ys = np.linspace(-1.3, 1.3, 131)
+    pts = np.stack([np.zeros_like(ys), ys, np.zeros_like(ys)], 1)
+    margin, esc = orc.escape_margin(fr, pts)
+    B = float(fr["bailout2"])
+    for y0, mg, e in zip(ys, margin, esc):
+        y, best, escaped = y0, np.inf, False
+        for _ in range(10):
+            y = abs(y) ** 8 + y0
+            best = min(best, abs(y * y - B) / B)
+            if y * y > B:
+                escaped = True
+                break
+        assert e == escaped, y0
+        assert mg == pytest.approx(best, rel=1e-9, abs=1e-12), y0
