@@ -161,6 +161,17 @@ def adjoint_leg(frt, dev, reps):
             "rel_err_target": 1e-3}
 
 
+def hardware_fp32(flop, launch_ms):
+    """FP32 FLOP the dominant kernel issues on active lanes per launch (rocprofv3
+    SQ_INSTS_VALU_FLOPS_FP32 x 64 x VALUUtilization, from the profile of the
+    same sources and launch configuration), over this run's launch time."""
+    if flop is None or launch_ms <= 0:
+        return None
+    tf = flop / (launch_ms * 1e-3) / 1e12
+    return {"flop_per_launch": flop, "tflops": tf, "frac": tf / FP32_VECTOR_PEAK_TFLOPS,
+            "frac_of_nonpacked": tf / FP32_NONPACKED_PEAK_TFLOPS}
+
+
 def measured_ceilings(frt, dev, achieved):
     """Sustained FP32 FMA and transcendental issue rates of this device under
     the build's code generation (packed FP32 off), from the library's rate
@@ -276,6 +287,7 @@ def main():
     achieved = stages[dom]["achieved_tflops"]
 
     traffic = None
+    hw_flop = None
     if os.path.exists(args.traffic):
         try:
             with open(args.traffic) as fh:
@@ -284,6 +296,7 @@ def main():
                     and tr.get("launch_config") == launch_cfg[variants[0]]
                     and tr.get("kernel_sources_sha256") == kernel_sources_sha256()):
                 traffic = tr.get("bytes_per_launch")
+                hw_flop = tr.get("hw_fp32_flop_per_launch")
         except (OSError, ValueError):
             traffic = None
 
@@ -317,6 +330,7 @@ def main():
                      "peak_nonpacked_fp32": FP32_NONPACKED_PEAK_TFLOPS,
                      "frac_of_nonpacked": achieved / FP32_NONPACKED_PEAK_TFLOPS},
         "stages": stages,
+        "hardware_fp32": hardware_fp32(hw_flop, stages[dom]["ms"]),
         "whole_path_tflops": float(flops.sum() / (ms_step * 1e-3) / 1e12),
         "launch_config": launch_cfg,
     }
