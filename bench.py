@@ -20,6 +20,7 @@ cores.
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -92,9 +93,31 @@ def cpu_baseline(jobs, target_s=20.0):
             break
     if stride != 16:
         n, dt = run(stride)
+    # one thread on the stride-16 sample (1/256 of the rays)
+    n1, dt1 = 0, 0.0
+    for v, job in enumerate(jobs):
+        pix = W.stratified_pixels(job["camera"]["width"], job["camera"]["height"], 16, seed=300 + v)
+        t0 = time.perf_counter()
+        orc.render(job, pixels=pix, threads=1)
+        dt1 += time.perf_counter() - t0
+        n1 += pix.size
     return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": orc.max_threads(), "kind": "oracle",
             "sample": "FP64 oracle (OpenMP over rays) on one pixel per %dx%d cell of each of the %d views "
-                      "(%d of %d rays, %.1f s), same normals and shadow rays" % (stride, stride, len(jobs), n, total, dt)}
+                      "(%d of %d rays, %.1f s), same normals and shadow rays" % (stride, stride, len(jobs), n, total, dt),
+            "single_core": {"value": n1 / dt1 / 1e6, "unit": "Mrays/s",
+                            "sample": "one thread, one pixel per 16x16 cell (%d rays, %.1f s)" % (n1, dt1)},
+            "cpu_model": host_cpu_model()}
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def adjoint_leg(frt, dev, reps):
