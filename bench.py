@@ -93,6 +93,7 @@ def cpu_baseline(jobs, target_s=20.0):
             break
     if stride != 16:
         n, dt = run(stride)
+    cores = orc.max_threads()
     # one thread on the stride-16 sample (1/256 of the rays)
     n1, dt1 = 0, 0.0
     for v, job in enumerate(jobs):
@@ -101,7 +102,7 @@ def cpu_baseline(jobs, target_s=20.0):
         orc.render(job, pixels=pix, threads=1)
         dt1 += time.perf_counter() - t0
         n1 += pix.size
-    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": orc.max_threads(), "kind": "oracle",
+    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": cores, "kind": "oracle",
             "sample": "FP64 oracle (OpenMP over rays) on one pixel per %dx%d cell of each of the %d views "
                       "(%d of %d rays, %.1f s), same normals and shadow rays" % (stride, stride, len(jobs), n, total, dt),
             "single_core": {"value": n1 / dt1 / 1e6, "unit": "Mrays/s",
