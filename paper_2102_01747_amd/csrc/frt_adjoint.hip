@@ -411,6 +411,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 // Reduce the wave's partial gradients for job j and add them to its outputs.
+// j: the job's index in the caller's arrays
 __device__ __forceinline__ void flush(const AdjointArgs& a, int j, float (&acc)[kGradSlots]) {
     const bool lead = (threadIdx.x & 63) == 0;
 #pragma unroll
@@ -425,33 +426,37 @@ __device__ __forceinline__ void flush(const AdjointArgs& a, int j, float (&acc)[
 }
 
 // One instantiation per fractal kind (the two tangent sets differ in size);
-// each drains the whole tile range through its own counter and skips the
-// tiles of jobs of the other kind.
+// each drains the 64-ray tiles of its kind's jobs, [range[KIND][0],
+// range[KIND][1]) of the ray index space, through its own counter.  A tile
+// lies inside one job, found through the wave's job cursor.
 template <int KIND>
 __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHeader* __restrict__ hdr) {
-    const unsigned long long tiles = hdr->total_rays >> 6;
+    const unsigned long long r0 = hdr->range[KIND][0];
+    const unsigned long long tiles = (hdr->range[KIND][1] - r0) >> 6;
     const int n_jobs = a.n_jobs;
     const int lane = threadIdx.x & 63;
     float acc[kGradSlots];
 #pragma unroll
     for (int s = 0; s < kGradSlots; ++s) acc[s] = 0.0f;
-    int cur = -1;   // job the partial sums belong to (uniform across the wave)
+    int cur = -1;   // caller's index of the job the partial sums belong to (uniform across the wave)
+    JobCursor jc;
     for (;;) {
         unsigned long long t = 0;
         if (lane == 0) t = atomicAdd(&hdr->adj_queue[KIND], 1ull);
         t = bcast_first(t);
         if (t >= tiles) break;
-        const long long g = static_cast<long long>(t << 6) + lane;
-        int j, px, py;
-        const bool in = ray_pixel<true>(a.jobs, a.jobs[0], n_jobs, g, j, px, py);
-        j = __builtin_amdgcn_readfirstlane(j);   // a tile lies inside one job
-        if (j != cur) {
-            if (cur >= 0) flush(a, cur, acc);
-            cur = j;
-        }
+        const unsigned long long g0 = r0 + (t << 6);
+        job_seek<true>(a.jobs, a.jobs[0], n_jobs, g0, jc);
+        const int j = jc.j;
         const JobDev& J = a.jobs[j];
         const AdjointJob& A = a.ajobs[j];
-        if (J.kind != KIND || !in) continue;
+        if (A.out_index != cur) {
+            if (cur >= 0) flush(a, cur, acc);
+            cur = A.out_index;
+        }
+        int px, py;
+        const bool in = tile_pixel(J, static_cast<long long>(g0 - jc.begin) + lane, px, py);
+        if (!in) continue;
         const long long NP = J.npix;
         const long long p = static_cast<long long>(py) * J.width + px;
         const int st = J.status[p];

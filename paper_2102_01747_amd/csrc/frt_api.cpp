@@ -751,9 +751,8 @@ frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float*
     if (!grad_c || !grad_power || !grad_plane) return fail(FRT_EINVAL, "null gradient output");
     frt_status s = check_workspace(workspace, ws_bytes, n_jobs);
     if (s != FRT_OK) return s;
-    std::vector<JobDev> table(static_cast<size_t>(n_jobs));
-    std::vector<frt::AdjointJob> adj(static_cast<size_t>(n_jobs));
-    int64_t begin = 0;
+    std::vector<JobDev> packed(static_cast<size_t>(n_jobs));
+    std::vector<frt::AdjointJob> adj_in(static_cast<size_t>(n_jobs));
     for (int i = 0; i < n_jobs; ++i) {
         std::string why;
         const frt_job& jb = jobs[i];
@@ -766,18 +765,38 @@ frt_status frt_render_backward(const frt_job* jobs, int32_t n_jobs, const float*
         if (jb.march.normal_mode == FRT_NORMAL_ANALYTIC)
             return fail(FRT_EUNSUPPORTED, "job " + std::to_string(i) +
                                               ": the adjoint of analytic normals needs second derivatives");
-        pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, begin, table[size_t(i)]);
-        begin += table[size_t(i)].ray_count;
-        frt::AdjointJob& a = adj[size_t(i)];
+        pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, 0, packed[size_t(i)]);
+        frt::AdjointJob& a = adj_in[size_t(i)];
+        std::memset(&a, 0, sizeof(a));
         a.g_colour = g_colour ? g_colour[i] : nullptr;
         a.g_depth = g_depth ? g_depth[i] : nullptr;
         a.g_normal = g_normal ? g_normal[i] : nullptr;
         a.g_pixel = grad_pixel ? grad_pixel[i] : nullptr;
         for (int k = 0; k < 2; ++k)
             for (int e = 0; e < 3; ++e) a.raw_n[k][e] = k < jb.n_planes ? jb.planes[k].n[e] : 0.0f;
+        a.out_index = i;
     }
+    // the ray index space holds the Julia jobs, then the Mandelbulb jobs, so
+    // each kind's kernel drains only its own tiles
     WorkspaceHeader hdr;
     std::memset(&hdr, 0, sizeof(hdr));
+    std::vector<JobDev> table;
+    std::vector<frt::AdjointJob> adj;
+    table.reserve(size_t(n_jobs));
+    adj.reserve(size_t(n_jobs));
+    int64_t begin = 0;
+    for (int kind = 0; kind < 2; ++kind) {
+        hdr.range[kind][0] = static_cast<unsigned long long>(begin);
+        for (int i = 0; i < n_jobs; ++i) {
+            if (packed[size_t(i)].kind != kind) continue;
+            JobDev J = packed[size_t(i)];
+            J.ray_begin = begin;
+            begin += J.ray_count;
+            table.push_back(J);
+            adj.push_back(adj_in[size_t(i)]);
+        }
+        hdr.range[kind][1] = static_cast<unsigned long long>(begin);
+    }
     hdr.total_rays = static_cast<unsigned long long>(begin);
     hdr.n_jobs = n_jobs;
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -102,6 +102,8 @@ struct AdjointJob {
     const float* g_normal;   // [3][P]
     float* g_pixel;          // [kGradSlots][P] per-pixel contributions (optional)
     float raw_n[2][3];       // raw plane normals (the job holds unit ones)
+    int32_t out_index;       // the job's index in the caller's arrays (gradient outputs)
+    int32_t pad;
 };
 
 // Workspace layout: a 1 KiB header, the job table, then the table of
@@ -112,7 +114,8 @@ struct AdjointJob {
 struct alignas(256) WorkspaceHeader {
     unsigned long long queue[kNumVariants][2];   // rays claimed: primary march, shadow march
     unsigned long long range[kNumVariants][2];   // each group's [begin, end) in the ray index space
-    unsigned long long adj_queue[2];             // 64-ray tiles claimed by the adjoint kernels (per kind)
+    unsigned long long adj_queue[2];             // 64-ray tiles claimed by the adjoint kernels (per kind;
+                                                 // kind k's rays are [range[k][0], range[k][1]) in a backward call)
     unsigned long long total_rays;
     int32_t n_jobs;
     int32_t pad[(1024 - 32 * kNumVariants - 28) / 4];
