@@ -42,6 +42,38 @@ constexpr int kMaxBodiesPerTrip = 64;
 
 enum MarchPhase : int { kIdle = 0, kCut = 1, kMarch = 2, kRefine = 3, kDone = 4 };
 
+// Results of a finished primary ray (R12's miss encoding; a cut-face hit takes
+// the plane's normal, other hits get theirs from the normal kernel).
+__device__ __forceinline__ void write_primary(const JobDev& J, int pix, int status, float t, int entry, int steps,
+                                              unsigned evals, unsigned bodies, int hit_it) {
+    const long long NP = J.npix;
+    const int cls = status & 7;
+    if (cls == kMissBounds || cls == kMissTmax) {
+        J.depth[pix] = -1.0f;
+        J.normal[pix] = 0.0f;
+        J.normal[NP + pix] = 0.0f;
+        J.normal[2 * NP + pix] = 0.0f;
+        J.colour[pix] = 0.0f;
+        J.colour[NP + pix] = 0.0f;
+        J.colour[2 * NP + pix] = 0.0f;
+    } else {
+        J.depth[pix] = t;
+        if (cls == kHitCut) {
+            J.normal[pix] = J.pn[entry][0];
+            J.normal[NP + pix] = J.pn[entry][1];
+            J.normal[2 * NP + pix] = J.pn[entry][2];
+        }
+    }
+    J.status[pix] = static_cast<uint8_t>(status);
+    if (J.counters) {
+        J.counters[pix] = static_cast<unsigned>(steps);
+        J.counters[NP + pix] = evals;
+        J.counters[2 * NP + pix] = bodies;
+        J.counters[3 * NP + pix] = static_cast<unsigned>(hit_it);
+        for (int k = 4; k < kCounterPlanes; ++k) J.counters[k * NP + pix] = 0u;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Persistent march kernel.  SHADOW = false: primary rays (interval, cut face,
 // march, refinement).  SHADOW = true: the shadow ray of every lit hit, from
@@ -95,34 +127,18 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
         if (m_busy == 0ull && m_done == 0ull && exhausted) break;
         const int waiting = __popcll(m_done) + (exhausted ? 0 : __popcll(__ballot(phase == kIdle)));
         if (m_busy == 0ull || waiting >= rare_lanes) {
+            const bool one_job = BATCH && !SHADOW && __ballot(phase == kDone && jb != cur.j) == 0ull;
             if (phase == kDone) {
                 const JobDev& J = job_ref<BATCH>(jobs, job1, jb);
                 const long long NP = J.npix;
                 if constexpr (!SHADOW) {
-                    const int cls = status & 7;
-                    if (cls == kMissBounds || cls == kMissTmax) {
-                        J.depth[pix] = -1.0f;
-                        J.normal[pix] = 0.0f;
-                        J.normal[NP + pix] = 0.0f;
-                        J.normal[2 * NP + pix] = 0.0f;
-                        J.colour[pix] = 0.0f;
-                        J.colour[NP + pix] = 0.0f;
-                        J.colour[2 * NP + pix] = 0.0f;
+                    // when the finished lanes all belong to the cursor's job
+                    // (the usual case) its output pointers come through scalar loads
+                    if (one_job) {
+                        write_primary(job_ref<BATCH>(jobs, job1, cur.j), pix, status, t, entry, steps, evals, bodies,
+                                      hit_it);
                     } else {
-                        J.depth[pix] = t;
-                        if (cls == kHitCut) {
-                            J.normal[pix] = J.pn[entry][0];
-                            J.normal[NP + pix] = J.pn[entry][1];
-                            J.normal[2 * NP + pix] = J.pn[entry][2];
-                        }
-                    }
-                    J.status[pix] = static_cast<uint8_t>(status);
-                    if (J.counters) {
-                        J.counters[pix] = static_cast<unsigned>(steps);
-                        J.counters[NP + pix] = evals;
-                        J.counters[2 * NP + pix] = bodies;
-                        J.counters[3 * NP + pix] = static_cast<unsigned>(hit_it);
-                        for (int k = 4; k < kCounterPlanes; ++k) J.counters[k * NP + pix] = 0u;
+                        write_primary(J, pix, status, t, entry, steps, evals, bodies, hit_it);
                     }
                 } else {
                     if (status & kFlagShadowed) {
