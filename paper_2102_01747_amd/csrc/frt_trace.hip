@@ -74,6 +74,22 @@ __device__ __forceinline__ void write_primary(const JobDev& J, int pix, int stat
     }
 }
 
+// Results of a finished shadow ray: a shadowed pixel keeps only the ambient
+// term of its colour.
+__device__ __forceinline__ void write_shadow(const JobDev& J, int pix, int status, unsigned evals, unsigned bodies) {
+    const long long NP = J.npix;
+    if (status & kFlagShadowed) {
+        J.status[pix] = static_cast<uint8_t>(J.status[pix] | kFlagShadowed);
+        J.colour[pix] = J.albedo[0] * J.k_a;
+        J.colour[NP + pix] = J.albedo[1] * J.k_a;
+        J.colour[2 * NP + pix] = J.albedo[2] * J.k_a;
+    }
+    if (J.counters) {
+        J.counters[6 * NP + pix] = evals;
+        J.counters[7 * NP + pix] = bodies;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Persistent march kernel.  SHADOW = false: primary rays (interval, cut face,
 // march, refinement).  SHADOW = true: the shadow ray of every lit hit, from
@@ -127,13 +143,12 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
         if (m_busy == 0ull && m_done == 0ull && exhausted) break;
         const int waiting = __popcll(m_done) + (exhausted ? 0 : __popcll(__ballot(phase == kIdle)));
         if (m_busy == 0ull || waiting >= rare_lanes) {
-            const bool one_job = BATCH && !SHADOW && __ballot(phase == kDone && jb != cur.j) == 0ull;
+            const bool one_job = BATCH && __ballot(phase == kDone && jb != cur.j) == 0ull;
+            // when the finished lanes all belong to the cursor's job (the
+            // usual case) its output pointers come through scalar loads
             if (phase == kDone) {
                 const JobDev& J = job_ref<BATCH>(jobs, job1, jb);
-                const long long NP = J.npix;
                 if constexpr (!SHADOW) {
-                    // when the finished lanes all belong to the cursor's job
-                    // (the usual case) its output pointers come through scalar loads
                     if (one_job) {
                         write_primary(job_ref<BATCH>(jobs, job1, cur.j), pix, status, t, entry, steps, evals, bodies,
                                       hit_it);
@@ -141,16 +156,8 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                         write_primary(J, pix, status, t, entry, steps, evals, bodies, hit_it);
                     }
                 } else {
-                    if (status & kFlagShadowed) {
-                        J.status[pix] = static_cast<uint8_t>(J.status[pix] | kFlagShadowed);
-                        J.colour[pix] = J.albedo[0] * J.k_a;
-                        J.colour[NP + pix] = J.albedo[1] * J.k_a;
-                        J.colour[2 * NP + pix] = J.albedo[2] * J.k_a;
-                    }
-                    if (J.counters) {
-                        J.counters[6 * NP + pix] = evals;
-                        J.counters[7 * NP + pix] = bodies;
-                    }
+                    if (one_job) write_shadow(job_ref<BATCH>(jobs, job1, cur.j), pix, status, evals, bodies);
+                    else write_shadow(J, pix, status, evals, bodies);
                 }
                 phase = kIdle;
             }
