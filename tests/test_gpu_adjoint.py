@@ -203,13 +203,15 @@ def test_batch_adjoint_equals_single_calls(frt):
     cots = [_cotangent(j, 20 + k) for k, j in enumerate(jobs)]
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     gb = frt.render_backward(jobs, frames, [t(c[0]) for c in cots], [t(c[1]) for c in cots],
-                             [t(c[2]) for c in cots], "cuda")
+                             [t(c[2]) for c in cots], "cuda", per_pixel=True)
     torch.cuda.synchronize()
     batch = np.concatenate([gb[0].cpu().numpy(), gb[1].cpu().numpy()[:, None],
                             gb[2].cpu().numpy().reshape(len(jobs), 8)], 1)
     for k, (j, f, c) in enumerate(zip(jobs, frames, cots)):
-        single = _gpu_backward(frt, j, f, *c)
+        single, single_px = _gpu_backward(frt, j, f, *c, per_pixel=True)
         assert np.allclose(batch[k], single, rtol=1e-4, atol=1e-5 * np.abs(single).max()), (k, batch[k], single)
+        # the per-pixel contributions involve no atomics: identical bit for bit
+        assert np.array_equal(gb[3][k].cpu().numpy(), single_px), k
 
 
 def test_autograd_function_matches_direct_call(frt):
