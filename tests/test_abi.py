@@ -88,3 +88,107 @@ def test_ctypes_layout_matches_c_header(tmp_path):
         assert got[cname] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got["%s.%s" % (cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_render_validation_on_the_host():
+    """Every check of a render's parameters and workspace runs before the
+    library touches a device, so each invalid case is host-testable: exact
+    status code and a message naming the field.  The output pointers are
+    fake and never dereferenced."""
+    import copy
+
+    import paper_2102_01747_amd as frt
+    import workloads as W
+
+    if not os.path.exists(frt.LIB_PATH):
+        pytest.skip("libfrt.so not built")
+    L = frt.lib()
+    fake = ctypes.c_void_p(0x10000)
+    out = frt.Frame(fake, fake, fake, fake, None)
+    ws = ctypes.c_void_p(0x100000)   # 256-byte aligned, never dereferenced
+    base = W.julia_view(width=16, height=16, planes=[W.plane([0.0, 0.0, 1.0], 0.1)])
+
+    def call(job, frame=out, workspace=ws, ws_bytes=1 << 20, n_planes=None):
+        planes, npl = frt.make_planes(job["planes"])
+        return L.frt_render(ctypes.byref(frt.make_camera(job["camera"])), ctypes.byref(frt.make_fractal(job["fractal"])),
+                            planes, npl if n_planes is None else n_planes, ctypes.byref(frt.make_march(job["march"])),
+                            frame, workspace, ws_bytes, None)
+
+    def case(edit, status, words, **kw):
+        job = copy.deepcopy(base)
+        edit(job)
+        assert call(job, **kw) == status, words
+        assert words.encode() in L.frt_last_error(), (words, L.frt_last_error())
+
+    def setitem(path, value):
+        def f(job):
+            d = job
+            for k in path[:-1]:
+                d = d[k]
+            d[path[-1]] = value
+        return f
+
+    case(setitem(("camera", "width"), 0), frt.FRT_EINVAL, "width and height")
+    case(setitem(("camera", "fov_y_deg"), 180.0), frt.FRT_EINVAL, "fov_y_deg")
+    case(setitem(("fractal", "c"), [float("nan"), 0.0, 0.0, 0.0]), frt.FRT_EINVAL, "non-finite fractal")
+    case(setitem(("fractal", "kind"), 7), frt.FRT_EINVAL, "unknown fractal kind")
+    case(setitem(("fractal", "power"), 17.0), frt.FRT_EINVAL, "Julia degree")
+    case(setitem(("fractal", "max_iter"), 0), frt.FRT_EINVAL, "max_iter")
+    case(setitem(("planes",), [W.plane([0.0, 0.0, 0.0], 0.1)]), frt.FRT_EINVAL, "plane normal is zero")
+    case(lambda j: None, frt.FRT_EINVAL, "n_planes", n_planes=3)
+    case(lambda j: j["march"].update(eps_abs=0.0, eps_rel=0.0), frt.FRT_EINVAL, "eps_abs and eps_rel")
+    case(setitem(("march", "step_clamp"), 0.0), frt.FRT_EINVAL, "step_clamp")
+    case(setitem(("march", "normal_mode"), 5), frt.FRT_EINVAL, "unknown normal_mode")
+    case(setitem(("march", "refine_iters"), 33), frt.FRT_EINVAL, "refine_iters")
+    case(lambda j: None, frt.FRT_EINVAL, "null output plane", frame=frt.Frame(fake, None, fake, fake, None))
+    case(lambda j: j.update(march=W.phong(j["march"])), frt.FRT_EUNSUPPORTED, "frt_render_scene")
+    # a valid job, then the workspace checks
+    case(lambda j: None, frt.FRT_EINVAL, "workspace is null", workspace=None)
+    case(lambda j: None, frt.FRT_EINVAL, "aligned", workspace=ctypes.c_void_p(0x100008))
+    case(lambda j: None, frt.FRT_ENOMEM, "workspace too small", ws_bytes=64)
+
+
+def test_batch_and_backward_validation_on_the_host():
+    """frt_render_batch names the first invalid job; frt_render_backward
+    refuses analytic normals and the closest-hit shading: all before any
+    device call (fake, never dereferenced pointers)."""
+    import copy
+
+    import paper_2102_01747_amd as frt
+    import workloads as W
+
+    if not os.path.exists(frt.LIB_PATH):
+        pytest.skip("libfrt.so not built")
+    L = frt.lib()
+    fake = ctypes.c_void_p(0x10000)
+    ws = ctypes.c_void_p(0x100000)
+    good = W.julia_view(width=16, height=16)
+    bad = copy.deepcopy(good)
+    bad["fractal"]["max_iter"] = 0
+
+    def table(jobs):
+        arr = (frt.Job * len(jobs))()
+        for k, j in enumerate(jobs):
+            planes, npl = frt.make_planes(j["planes"])
+            arr[k] = frt.Job(frt.make_camera(j["camera"]), frt.make_fractal(j["fractal"]), planes, npl,
+                             frt.make_march(j["march"]), frt.Frame(fake, fake, fake, fake, None))
+        return arr
+
+    arr = table([good, good, bad])
+    assert L.frt_render_batch(arr, 3, ws, 1 << 20, 0, None) == frt.FRT_EINVAL
+    assert b"job 2" in L.frt_last_error() and b"max_iter" in L.frt_last_error()
+    assert L.frt_render_batch(table([good]), 1, ws, 1 << 20, 2, None) == frt.FRT_EINVAL   # use_graph
+    assert L.frt_render_batch(table([good]), 1, ws, 64, 0, None) == frt.FRT_ENOMEM
+
+    analytic = copy.deepcopy(good)
+    analytic["march"]["normal_mode"] = "analytic"
+    g = ctypes.c_void_p(0x200000)
+    assert L.frt_render_backward(table([good, analytic]), 2, None, None, None, None, g, g, g, ws, 1 << 20,
+                                 None) == frt.FRT_EUNSUPPORTED
+    assert b"job 1" in L.frt_last_error() and b"second derivatives" in L.frt_last_error()
+    phong = copy.deepcopy(good)
+    phong["march"] = W.phong(phong["march"])
+    assert L.frt_render_backward(table([phong]), 1, None, None, None, None, g, g, g, ws, 1 << 20,
+                                 None) == frt.FRT_EUNSUPPORTED
+    assert L.frt_render_backward(table([good]), 1, None, None, None, None, None, g, g, ws, 1 << 20,
+                                 None) == frt.FRT_EINVAL
