@@ -51,12 +51,18 @@ KERNEL_SOURCES = ("frt_trace.hip", "frt_fractal.hpp", "frt_math.hpp", "frt_ray.h
 
 
 def kernel_sources_sha256():
+    """SHA-256 of the forward kernels' code: the sources with comments and
+    whitespace removed, so that an edit of a comment keeps the profiled
+    figures (the sources hold no string literal with a comment marker)."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2102_01747_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2102_01747_amd", "csrc", name)) as fh:
+            code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 

@@ -107,15 +107,17 @@ struct AdjointJob {
 };
 
 // Workspace layout: a 1 KiB header, the job table, then the table of
-// upstream-gradient pointers (AdjointJob, read by the adjoint only).  The jobs
-// of a batch are laid out in the ray index space variant by variant; group v
-// holds the rays [range[v][0], range[v][1]) and drains them through its own
-// counters (one for the primary march, one for the shadow march).
+// upstream-gradient pointers (AdjointJob, read by the adjoint only).  In a
+// forward call the jobs are laid out in the ray index space variant by
+// variant; group v holds the rays [range[v][0], range[v][1]) and drains them
+// through its own counters (one for the primary march, one for the shadow
+// march).  In a backward call they are laid out kind by kind (Julia, then
+// Mandelbulb), and range[k] holds kind k's rays.  Either way the table is in
+// ray order, so a ray's job is found by a search over ray_begin.
 struct alignas(256) WorkspaceHeader {
     unsigned long long queue[kNumVariants][2];   // rays claimed: primary march, shadow march
     unsigned long long range[kNumVariants][2];   // each group's [begin, end) in the ray index space
-    unsigned long long adj_queue[2];             // 64-ray tiles claimed by the adjoint kernels (per kind;
-                                                 // kind k's rays are [range[k][0], range[k][1]) in a backward call)
+    unsigned long long adj_queue[2];             // 64-ray tiles claimed by the adjoint kernels (per kind)
     unsigned long long total_rays;
     int32_t n_jobs;
     int32_t pad[(1024 - 32 * kNumVariants - 28) / 4];
