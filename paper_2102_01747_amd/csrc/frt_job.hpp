@@ -115,7 +115,7 @@ struct AdjointJob {
 // Mandelbulb), and range[k] holds kind k's rays.  Either way the table is in
 // ray order, so a ray's job is found by a search over ray_begin.
 struct alignas(256) WorkspaceHeader {
-    unsigned long long queue[kNumVariants][2];   // rays claimed: primary march, shadow march
+    unsigned long long queue[kNumVariants][2];   // chunks claimed beyond each wave's first: primary, shadow march
     unsigned long long range[kNumVariants][2];   // each group's [begin, end) in the ray index space
     unsigned long long adj_queue[2];             // 64-ray tiles claimed by the adjoint kernels (per kind)
     unsigned long long total_rays;

@@ -112,6 +112,26 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
     }
     unsigned long long q_next = 0, q_end = 0;   // wave-uniform window of claimed rays
     bool drained = false;
+    // A wave's first claim is chunk number (its index in the grid), taken
+    // without the counter; the counter then hands out the chunks after the
+    // grid's first n_waves.  All waves claiming through one counter at the
+    // launch's start would queue on it: one address serves about 80
+    // device-scope atomics per microsecond.
+    const unsigned wpb = blockDim.x >> 6;
+    const unsigned long long n_waves = static_cast<unsigned long long>(gridDim.x) * wpb;
+    const unsigned long long first_chunk =
+        static_cast<unsigned long long>(blockIdx.x) * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    bool first_claim = true;
+    auto claim = [&]() -> unsigned long long {
+        unsigned long long k = first_chunk;
+        if (!first_claim) {
+            unsigned long long a = 0;
+            if (__lane_id() == 0) a = atomicAdd(queue, 1ull);
+            k = n_waves + bcast_first(a);
+        }
+        first_claim = false;
+        return r_begin + k * static_cast<unsigned long long>(chunk);
+    };
     JobCursor cur;                               // job of the current claim (wave-uniform)
     // shadow rays: the current tile's first ray index and the mask of its
     // shadow-casting pixels not yet handed to a lane (wave-uniform)
@@ -166,9 +186,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
             if constexpr (!SHADOW) {
             while (idle != 0ull && !drained) {
                 if (q_next >= q_end) {
-                    unsigned long long base = 0;
-                    if (__lane_id() == 0) base = atomicAdd(queue, static_cast<unsigned long long>(chunk));
-                    base = r_begin + bcast_first(base);
+                    const unsigned long long base = claim();
                     if (base >= r_end) {
                         drained = true;
                         continue;
@@ -243,9 +261,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
             while (idle != 0ull && (tmask != 0ull || !drained)) {
                 if (tmask == 0ull) {
                     if (q_next >= q_end) {
-                        unsigned long long base = 0;
-                        if (__lane_id() == 0) base = atomicAdd(queue, static_cast<unsigned long long>(chunk));
-                        base = r_begin + bcast_first(base);
+                        const unsigned long long base = claim();
                         if (base >= r_end) {
                             drained = true;
                             break;
