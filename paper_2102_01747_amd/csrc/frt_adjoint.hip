@@ -425,10 +425,17 @@ __device__ __forceinline__ void flush(const AdjointArgs& a, int j, float (&acc)[
     }
 }
 
+// Tiles per claim of the adjoint's counter.
+constexpr unsigned kAdjTiles = 4;
+
 // One instantiation per fractal kind (the two tangent sets differ in size);
 // each drains the 64-ray tiles of its kind's jobs, [range[KIND][0],
-// range[KIND][1]) of the ray index space, through its own counter.  A tile
-// lies inside one job, found through the wave's job cursor.
+// range[KIND][1]) of the ray index space, kAdjTiles at a time.  A wave's
+// first group is the one of its index in the grid; the kind's counter hands
+// out the groups after the grid's first n_waves (one address serves about 80
+// device-scope atomics per microsecond, so a claim per tile, and all waves
+// claiming at the start, would queue on it).  A tile lies inside one job,
+// found through the wave's job cursor.
 template <int KIND>
 __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHeader* __restrict__ hdr) {
     const unsigned long long r0 = hdr->range[KIND][0];
@@ -440,74 +447,83 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHe
     for (int s = 0; s < kGradSlots; ++s) acc[s] = 0.0f;
     int cur = -1;   // caller's index of the job the partial sums belong to (uniform across the wave)
     JobCursor jc;
-    for (;;) {
-        unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(&hdr->adj_queue[KIND], 1ull);
-        t = bcast_first(t);
-        if (t >= tiles) break;
-        const unsigned long long g0 = r0 + (t << 6);
-        job_seek<true>(a.jobs, a.jobs[0], n_jobs, g0, jc);
-        const int j = jc.j;
-        const JobDev& J = a.jobs[j];
-        const AdjointJob& A = a.ajobs[j];
-        if (A.out_index != cur) {
-            if (cur >= 0) flush(a, cur, acc);
-            cur = A.out_index;
+    const unsigned long long n_waves = static_cast<unsigned long long>(gridDim.x) * (blockDim.x >> 6);
+    unsigned long long grp =
+        static_cast<unsigned long long>(blockIdx.x) * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (bool first = true;; first = false) {
+        if (!first) {
+            unsigned long long c = 0;
+            if (lane == 0) c = atomicAdd(&hdr->adj_queue[KIND], 1ull);
+            grp = n_waves + bcast_first(c);
         }
-        int px, py;
-        const bool in = tile_pixel(J, static_cast<long long>(g0 - jc.begin) + lane, px, py);
-        if (!in) continue;
-        const long long NP = J.npix;
-        const long long p = static_cast<long long>(py) * J.width + px;
-        const int st = J.status[p];
-        const int cls = st & 7;
-        const bool smooth = cls == kHitCut || (cls == kHit && !(st & kFlagUnrefined));
-        if (A.g_pixel) {
-            for (int s = 0; s < kGradSlots; ++s) A.g_pixel[s * NP + p] = 0.0f;
-        }
-        if (!smooth) continue;
-        const bool lit = !(st & kFlagShadowed);
-        const float gd = A.g_depth ? A.g_depth[p] : 0.0f;
-        bool any = gd != 0.0f;
-        if (A.g_colour) any = any || A.g_colour[p] != 0.0f || A.g_colour[NP + p] != 0.0f || A.g_colour[2 * NP + p] != 0.0f;
-        if (A.g_normal) any = any || A.g_normal[p] != 0.0f || A.g_normal[NP + p] != 0.0f || A.g_normal[2 * NP + p] != 0.0f;
-        if (!any) continue;   // nothing flows into this pixel
-        if (cls == kHitCut) {
-            // entry plane as the forward pass found it (float32 ray)
-            float dx, dy, dz;
-            primary_dir(J, px, py, dx, dy, dz);
-            float lo, hi;
-            int e;
-            const bool ok = ray_interval(J, J.eye[0], J.eye[1], J.eye[2], dx, dy, dz, J.eps_abs, lo, hi, e);
-            if (ok && e >= 0) {
-                float pa[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                cut_face_grad(J, A, p, NP, lit, e, px, py, gd, pa);
-                drop_nonfinite(pa);
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    if (e == 0) acc[5 + s] += pa[s]; else acc[9 + s] += pa[s];
-                }
-                if (A.g_pixel) {
-                    for (int s = 0; s < 4; ++s) A.g_pixel[(5 + 4 * e + s) * NP + p] = pa[s];
-                }
+        const unsigned long long t0 = grp * kAdjTiles;
+        if (t0 >= tiles) break;
+        const unsigned long long t1 = min(t0 + kAdjTiles, tiles);
+        for (unsigned long long t = t0; t < t1; ++t) {
+            const unsigned long long g0 = r0 + (t << 6);
+            job_seek<true>(a.jobs, a.jobs[0], n_jobs, g0, jc);
+            const int j = jc.j;
+            const JobDev& J = a.jobs[j];
+            const AdjointJob& A = a.ajobs[j];
+            if (A.out_index != cur) {
+                if (cur >= 0) flush(a, cur, acc);
+                cur = A.out_index;
             }
-        } else {
-            const OrbitParams P = orbit_params(J);
-            if constexpr (KIND == kJulia) {
-                float pa[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                surface_hit_grad<kJulia, 4>(J, A, P, p, NP, lit, px, py, J.depth[p], gd, pa);
-                drop_nonfinite(pa);
-#pragma unroll
-                for (int s = 0; s < 4; ++s) acc[s] += pa[s];
-                if (A.g_pixel) {
-                    for (int s = 0; s < 4; ++s) A.g_pixel[s * NP + p] = pa[s];
+            int px, py;
+            const bool in = tile_pixel(J, static_cast<long long>(g0 - jc.begin) + lane, px, py);
+            if (!in) continue;
+            const long long NP = J.npix;
+            const long long p = static_cast<long long>(py) * J.width + px;
+            const int st = J.status[p];
+            const int cls = st & 7;
+            const bool smooth = cls == kHitCut || (cls == kHit && !(st & kFlagUnrefined));
+            if (A.g_pixel) {
+                for (int s = 0; s < kGradSlots; ++s) A.g_pixel[s * NP + p] = 0.0f;
+            }
+            if (!smooth) continue;
+            const bool lit = !(st & kFlagShadowed);
+            const float gd = A.g_depth ? A.g_depth[p] : 0.0f;
+            bool any = gd != 0.0f;
+            if (A.g_colour) any = any || A.g_colour[p] != 0.0f || A.g_colour[NP + p] != 0.0f || A.g_colour[2 * NP + p] != 0.0f;
+            if (A.g_normal) any = any || A.g_normal[p] != 0.0f || A.g_normal[NP + p] != 0.0f || A.g_normal[2 * NP + p] != 0.0f;
+            if (!any) continue;   // nothing flows into this pixel
+            if (cls == kHitCut) {
+                // entry plane as the forward pass found it (float32 ray)
+                float dx, dy, dz;
+                primary_dir(J, px, py, dx, dy, dz);
+                float lo, hi;
+                int e;
+                const bool ok = ray_interval(J, J.eye[0], J.eye[1], J.eye[2], dx, dy, dz, J.eps_abs, lo, hi, e);
+                if (ok && e >= 0) {
+                    float pa[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    cut_face_grad(J, A, p, NP, lit, e, px, py, gd, pa);
+                    drop_nonfinite(pa);
+    #pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        if (e == 0) acc[5 + s] += pa[s]; else acc[9 + s] += pa[s];
+                    }
+                    if (A.g_pixel) {
+                        for (int s = 0; s < 4; ++s) A.g_pixel[(5 + 4 * e + s) * NP + p] = pa[s];
+                    }
                 }
             } else {
-                float pa[1] = {0.0f};
-                surface_hit_grad<kBulb, 1>(J, A, P, p, NP, lit, px, py, J.depth[p], gd, pa);
-                drop_nonfinite(pa);
-                acc[4] += pa[0];
-                if (A.g_pixel) A.g_pixel[4 * NP + p] = pa[0];
+                const OrbitParams P = orbit_params(J);
+                if constexpr (KIND == kJulia) {
+                    float pa[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    surface_hit_grad<kJulia, 4>(J, A, P, p, NP, lit, px, py, J.depth[p], gd, pa);
+                    drop_nonfinite(pa);
+    #pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[s] += pa[s];
+                    if (A.g_pixel) {
+                        for (int s = 0; s < 4; ++s) A.g_pixel[s * NP + p] = pa[s];
+                    }
+                } else {
+                    float pa[1] = {0.0f};
+                    surface_hit_grad<kBulb, 1>(J, A, P, p, NP, lit, px, py, J.depth[p], gd, pa);
+                    drop_nonfinite(pa);
+                    acc[4] += pa[0];
+                    if (A.g_pixel) A.g_pixel[4 * NP + p] = pa[0];
+                }
             }
         }
     }
