@@ -114,14 +114,23 @@ struct AdjointJob {
 // march).  In a backward call they are laid out kind by kind (Julia, then
 // Mandelbulb), and range[k] holds kind k's rays.  Either way the table is in
 // ray order, so a ray's job is found by a search over ray_begin.
+// Claim counters per variant and stage: one per group of workgroups (blocks
+// are dealt to the XCDs in turn, so block b's group is b mod kQueueSlots),
+// each on its own 256-byte line: one address serves about 80 device-scope
+// atomics per microsecond, eight addresses about 540.
+constexpr int kQueueSlots = 8;
+
 struct alignas(256) WorkspaceHeader {
-    unsigned long long queue[kNumVariants][2];   // chunks claimed beyond each wave's first: primary, shadow march
     unsigned long long range[kNumVariants][2];   // each group's [begin, end) in the ray index space
-    unsigned long long adj_queue[2];             // 64-ray tiles claimed by the adjoint kernels (per kind)
+    unsigned long long adj_queue[2];             // tile groups claimed by the adjoint kernels (per kind)
     unsigned long long total_rays;
     int32_t n_jobs;
-    int32_t pad[(1024 - 32 * kNumVariants - 28) / 4];
+    int32_t pad[(1024 - 16 * kNumVariants - 28) / 4];
+    // [(variant * 2 + stage) * kQueueSlots + slot][0]: chunks claimed from
+    // that slot's share (stage 0 primary march, 1 shadow march)
+    unsigned long long queue[kNumVariants * 2 * kQueueSlots][32];
 };
-static_assert(sizeof(WorkspaceHeader) == 1024, "workspace header must be 1 KiB");
+static_assert(sizeof(WorkspaceHeader) == 1024 + kNumVariants * 2 * kQueueSlots * 256,
+              "workspace header: 1 KiB of fields, then the claim counters");
 
 }  // namespace frt

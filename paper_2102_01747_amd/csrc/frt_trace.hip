@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
                                                     int orbit_lanes, int rare_lanes) {
     using Orbit = typename OrbitOf<VAR>::T;
     // this variant's group of rays and its counter
-    unsigned long long* queue = &hdr->queue[VAR][SHADOW ? 1 : 0];
+    unsigned long long* queue = &hdr->queue[(VAR * 2 + (SHADOW ? 1 : 0)) * kQueueSlots][0];
     int n_jobs = 1;
     unsigned long long r_begin = 0, r_end = static_cast<unsigned long long>(job1.ray_count);
     if constexpr (BATCH) {
@@ -113,24 +113,34 @@ __global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ j
     unsigned long long q_next = 0, q_end = 0;   // wave-uniform window of claimed rays
     bool drained = false;
     // A wave's first claim is chunk number (its index in the grid), taken
-    // without the counter; the counter then hands out the chunks after the
-    // grid's first n_waves.  All waves claiming through one counter at the
-    // launch's start would queue on it: one address serves about 80
-    // device-scope atomics per microsecond.
+    // without a counter.  The chunks after the grid's first n_waves are
+    // dealt to kQueueSlots counters in turn (chunk n_waves + s + j
+    // kQueueSlots is the j-th of slot s); a wave claims from its block's
+    // slot, and from the others once that share is spent.  All waves
+    // claiming through one address would queue on it.
     const unsigned wpb = blockDim.x >> 6;
     const unsigned long long n_waves = static_cast<unsigned long long>(gridDim.x) * wpb;
     const unsigned long long first_chunk =
         static_cast<unsigned long long>(blockIdx.x) * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned home = blockIdx.x % kQueueSlots;
+    unsigned spent = 0u;   // slots whose share is spent (wave-uniform)
     bool first_claim = true;
-    auto claim = [&]() -> unsigned long long {
-        unsigned long long k = first_chunk;
-        if (!first_claim) {
-            unsigned long long a = 0;
-            if (__lane_id() == 0) a = atomicAdd(queue, 1ull);
-            k = n_waves + bcast_first(a);
+    auto claim = [&]() -> unsigned long long {   // the chunk's first ray, or r_end
+        if (first_claim) {
+            first_claim = false;
+            return min(r_begin + first_chunk * static_cast<unsigned long long>(chunk), r_end);
         }
-        first_claim = false;
-        return r_begin + k * static_cast<unsigned long long>(chunk);
+        for (unsigned i = 0; i < static_cast<unsigned>(kQueueSlots); ++i) {
+            const unsigned sl = (home + i) % kQueueSlots;
+            if (spent & (1u << sl)) continue;
+            unsigned long long a = 0;
+            if (__lane_id() == 0) a = atomicAdd(queue + 32 * sl, 1ull);
+            const unsigned long long k = n_waves + sl + bcast_first(a) * kQueueSlots;
+            const unsigned long long base = r_begin + k * static_cast<unsigned long long>(chunk);
+            if (base < r_end) return base;
+            spent |= 1u << sl;
+        }
+        return r_end;
     };
     JobCursor cur;                               // job of the current claim (wave-uniform)
     // shadow rays: the current tile's first ray index and the mask of its
@@ -506,7 +516,7 @@ __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ 
 }
 
 __global__ void reset_queue_kernel(WorkspaceHeader* hdr) {
-    if (threadIdx.x < 2 * kNumVariants) hdr->queue[threadIdx.x >> 1][threadIdx.x & 1] = 0ull;
+    if (threadIdx.x < 2 * kNumVariants * kQueueSlots) hdr->queue[threadIdx.x][0] = 0ull;
 }
 
 static hipError_t mark(hipEvent_t* marks, int k, hipStream_t stream) {
@@ -561,7 +571,7 @@ const void* trace_kernel_symbol(int variant, bool batch) {
 
 hipError_t launch_trace(const TraceGroup* groups, int n_groups, bool batch, const JobDev* jobs, const JobDev& job1,
                         WorkspaceHeader* hdr, hipStream_t stream, hipEvent_t* marks) {
-    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, stream, hdr);
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(2 * kNumVariants * kQueueSlots), 0, stream, hdr);
     hipError_t e = hipGetLastError();
     for (int stage = 0; stage < 3 && e == hipSuccess; ++stage) {
         e = mark(marks, stage, stream);
