@@ -96,8 +96,12 @@ __device__ __forceinline__ void write_shadow(const JobDev& J, int pix, int statu
 // p* + 4 eps(t*) N toward the light with threshold eps(t*) (the hit is read
 // back from depth / normal / status written by the earlier kernels).
 // ---------------------------------------------------------------------------
+// The primary march of every variant but n = 8 is held to 64 VGPRs (8 waves
+// per SIMD): left alone the real-power kernel took 66 and ran its 4K sweep
+// about 1.5% slower; the n = 8 kernel fits anyway and was faster without it.
 template <int VAR, bool BATCH, bool SHADOW>
-__global__ void __launch_bounds__(512) march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SHADOW || VAR == kVarBulb8 ? 1 : 8)))
+march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                                                     WorkspaceHeader* __restrict__ hdr, int chunk,
                                                     int orbit_lanes, int rare_lanes) {
     using Orbit = typename OrbitOf<VAR>::T;
