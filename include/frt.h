@@ -254,8 +254,8 @@ typedef struct {
     float scale;
 } frt_object;
 
-/* Device workspace of frt_render_scene over n_objects objects (a 1 KiB
- * header and the object table), 256-byte aligned.                          */
+/* Device workspace of frt_render_scene over n_objects objects (the
+ * workspace header and the object table), 256-byte aligned.                 */
 size_t frt_scene_workspace_bytes(int32_t n_objects);
 
 /* Render one view of a scene of n_objects (1..16) objects in one launch.
