@@ -138,6 +138,17 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
             const unsigned sl = (home + i) % kQueueSlots;
             if (spent & (1u << sl)) continue;
             unsigned long long a = 0;
+            if (i > 0) {
+                // another slot: most are spent by the time a wave looks, so
+                // read the counter first (it only grows, so a stale value can
+                // only cost an extra attempt) instead of queueing an update
+                if (__lane_id() == 0) a = __hip_atomic_load(queue + 32 * sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                a = bcast_first(a);
+                if (r_begin + (n_waves + sl + a * kQueueSlots) * static_cast<unsigned long long>(chunk) >= r_end) {
+                    spent |= 1u << sl;
+                    continue;
+                }
+            }
             if (__lane_id() == 0) a = atomicAdd(queue + 32 * sl, 1ull);
             const unsigned long long k = n_waves + sl + bcast_first(a) * kQueueSlots;
             const unsigned long long base = r_begin + k * static_cast<unsigned long long>(chunk);
