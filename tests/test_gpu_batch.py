@@ -170,3 +170,47 @@ def test_batch_speedup_over_one_by_one(frt, batch_jobs):
     print("64 renders: one by one %.3f ms, batched %.3f ms (x%.2f), graph %.3f ms (x%.2f)"
           % (t_single, t_batch, t_single / t_batch, t_graph, t_single / t_graph))
     assert t_batch < t_single
+
+
+@pytest.mark.parametrize("block,chunk", [(64, 64), (128, 256), (512, 1024), (256, 64)])
+def test_every_ray_claimed_under_any_launch_shape(frt, block, chunk):
+    """The queue hands every chunk out: each wave's first chunk by its index
+    in the grid, the rest through eight counters that waves drain and then
+    steal from.  Output planes prefilled with sentinels must be fully
+    written for any chunk and block size, including grids of fewer blocks
+    than counters (tiny renders), and must equal the default launch's
+    output bit for bit."""
+    jobs = _tiny_jobs()[:12] + [W.bulb_view(0.7, 0.2, width=333, height=101, shadow=True),
+                                W.julia_view(width=200, height=120, shadow=True,
+                                             planes=[W.plane([0.2, 1.0, 0.3], 0.05)])]
+    ref = frt.render_batch(jobs, "cuda")
+    torch.cuda.synchronize()
+    variants = ("julia", "bulb_real", "bulb_int", "bulb8", "julia_deg")
+    saved = {v: frt.autotune_get(v) for v in variants}
+    try:
+        for v in variants:
+            b, c, w, o, r = saved[v]
+            frt.autotune_set(v, block, chunk, w, o, r)
+        outs = [frt.alloc_frame(j, "cuda") for j in jobs]
+        for f in outs:
+            f["depth"].fill_(float("nan"))
+            f["normal"].fill_(float("nan"))
+            f["colour"].fill_(float("nan"))
+            f["status"].fill_(255)
+        frt.render_batch(jobs, "cuda", outs=outs)
+        # one render alone too (its own grid, often below eight blocks)
+        single = frt.alloc_frame(jobs[3], "cuda")
+        single["status"].fill_(255)
+        single["depth"].fill_(float("nan"))
+        frt.render(jobs[3], "cuda", out=single)
+        torch.cuda.synchronize()
+    finally:
+        for v in variants:
+            frt.autotune_set(v, *saved[v])
+    for k, (f, g) in enumerate(zip(outs, ref)):
+        assert not torch.isnan(f["depth"]).any() and not torch.isnan(f["colour"]).any(), k
+        assert not (f["status"] == 255).any(), k
+        for plane in ("depth", "normal", "colour", "status"):
+            assert torch.equal(f[plane], g[plane]), (k, plane)
+    assert not (single["status"] == 255).any() and not torch.isnan(single["depth"]).any()
+    assert torch.equal(single["depth"], ref[3]["depth"])
