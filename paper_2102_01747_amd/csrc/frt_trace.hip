@@ -375,7 +375,11 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
         live |= __ballot(rearm);
         rearm = false;
         if (live != 0ull) {
-            const int keep = max(orbit_lanes, 1);
+            // Fewer lanes iterating than orbit_lanes happens only once the
+            // queue has run dry (otherwise the refill above has run): then
+            // every orbit runs to its end before the step, instead of the
+            // last rays of a launch paying the step path after every body.
+            const int keep = __popcll(live) < orbit_lanes ? 1 : orbit_lanes;
             int b = 0;
             do {
                 live = orb.step(P, live);
