@@ -45,10 +45,15 @@
  *       Phong/Fresnel closest-hit shader.
  *
  * Pins: the test suite ties every function here to closed forms, symmetries,
- * special cases or brute force, except two rounding probes, which perturb
- * each orbit body on purpose and only decide where the comparison tolerates
- * rounding: oracle_normal_perturbed and oracle_trap_perturbed are parity
- * unpinned.
+ * special cases or brute force.  The Mandelbulb running derivative is pinned
+ * on the positive polar axis, where the orbit is the real map y <- y^n + c
+ * and dr must be its exact c-derivative.  The two rounding probes
+ * (oracle_normal_perturbed, oracle_trap_perturbed) perturb each orbit body on
+ * purpose; they are pinned only as far as a probe can be: with a zero
+ * perturbation they reproduce the plain normal and trap bit for bit, they
+ * converge to them as the perturbation shrinks, and their factor is uniform
+ * on the stated interval.  How well a probe models float32 rounding is an
+ * assumption of the comparison masks, not a pinned fact.
  */
 #include <math.h>
 #include <stdint.h>
@@ -298,6 +303,12 @@ static double noise(uint64_t seed, uint64_t point, int body, int comp, double re
     uint64_t h = splitmix64(seed ^ splitmix64(point * 0x100000001B3ull + (uint64_t)body * 8u + (uint64_t)comp));
     double u = (double)(h >> 11) * (1.0 / 9007199254740992.0);   /* [0, 1) */
     return 1.0 + rel * (2.0 * u - 1.0);
+}
+
+/* The probe's factor for one (seed, point, body, component), exported so
+ * that the tests can check its distribution.                               */
+double oracle_probe_noise(uint64_t seed, uint64_t point, int32_t body, int32_t comp, double rel) {
+    return noise(seed, point, body, comp, rel);
 }
 
 static double perturbed_de(const or_fractal* f, const double p[3], double rel, uint64_t seed, uint64_t key) {

@@ -116,6 +116,9 @@ def lib():
         L.oracle_normal_perturbed.argtypes = [P(Fractal), dp, dp, dp, ctypes.c_int64, ctypes.c_int32,
                                               ctypes.c_double, ctypes.c_uint64, dp]
         L.oracle_normal_at.argtypes = [P(Fractal), dp, dp, dp, ctypes.c_int64, ctypes.c_int32, dp]
+        L.oracle_probe_noise.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_double]
+        L.oracle_probe_noise.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -539,6 +542,12 @@ def _phong_spec(nrm, L, V, ndl, shininess):
     direction, zero where the light is behind the surface."""
     Rl = 2.0 * ndl[:, None] * nrm - L[None, :]
     return np.where(ndl > 0.0, np.maximum(0.0, np.einsum("ij,ij->i", Rl, V)) ** shininess, 0.0)
+
+
+def probe_noise(seed, point, body, comp, rel):
+    """The rounding probes' multiplicative factor for one (seed, point, body,
+    component): uniform on [1 - rel, 1 + rel]."""
+    return lib().oracle_probe_noise(int(seed), int(point), int(body), int(comp), float(rel))
 
 
 def orbit_trap_perturbed(fractal, points, rel, seed):

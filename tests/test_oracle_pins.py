@@ -633,3 +633,115 @@ def test_escape_margin_bulb_polar_axis(orc):
                 break
         assert e == escaped, y0
         assert mg == pytest.approx(best, rel=1e-9, abs=1e-12), y0
+
+
+# ------------------------------------------------- Mandelbulb running derivative
+def _axis_map_complex_step(y0, n, max_iter, bailout2, h=1e-30):
+    """The real map y <- y^n + c from y = c (c = y0 > 0), run with c = y0 + i h
+    (complex step): Re(y) is the orbit, Im(y)/h its exact c-derivative to
+    rounding, with no difference quotient.  Returns (y, dy/dc, bodies that
+    stayed within the bailout)."""
+    c = complex(y0, h)
+    y, k = c, 0
+    for _ in range(max_iter):
+        y = y ** n + c
+        if y.real * y.real > bailout2:
+            break
+        k += 1
+    return y.real, y.imag / h, k
+
+
+@pytest.mark.parametrize("n", [2.0, 5.0, 8.0, 6.37])
+def test_bulb_running_derivative_is_the_axis_map_c_derivative(orc, n):
+    """On the positive polar axis, c = (0, y0, 0) with y0 > 0, every body has
+    theta = 0, so w^n = (0, r^n, 0) and the orbit is the real map y <- y^n + c
+    started at y = c (Listing 7 starts the orbit at the point itself).  The
+    running derivative dr <- n r^(n-1) dr + 1, dr = 1 (Sec. 2, Eq. 4 in norm,
+    with the +1 of the added point) is then exactly the c-derivative of that
+    map, which the test takes by complex step; the estimate is
+    d = 0.5 |y| ln|y| / y' (the constant of Listings 4 and 7).  n = 2 with
+    c in (0, 1/4] stays bounded (the Mandelbrot interval), so the estimate
+    there is negative; larger c and n = 5, 8 cover every escape body."""
+    if n == 2.0:
+        ys = np.concatenate([np.linspace(0.01, 0.25, 25), np.linspace(0.26, 1.2, 48)])
+    else:
+        ys = np.linspace(0.02, 1.2, 119)
+    for max_iter in (1, 3, 10, 15):
+        fr = W.bulb(n, max_iter)
+        B = float(fr["bailout2"])
+        pts = np.stack([np.zeros_like(ys), ys, np.zeros_like(ys)], 1)
+        d, it, m2, dr = orc.de(fr, pts)
+        bodies = set()
+        for k, y0 in enumerate(ys):
+            y, dy, esc = _axis_map_complex_step(float(y0), float(fr["power"]), max_iter, B)
+            bodies.add(esc)
+            assert it[k] == esc, (n, max_iter, y0)
+            assert m2[k] == pytest.approx(y * y, rel=1e-11), (n, max_iter, y0)
+            assert dr[k] == pytest.approx(dy, rel=1e-11), (n, max_iter, y0)
+            assert d[k] == pytest.approx(0.5 * abs(y) * math.log(abs(y)) / dy, rel=1e-10, abs=1e-300), (n, max_iter, y0)
+        if max_iter >= 10:
+            # the sample reaches escapes after 1, 2, ... bodies and non-escapes
+            assert len(bodies) >= 4, (n, max_iter, sorted(bodies))
+
+
+def test_bulb_running_derivative_is_not_the_orbit_derivative_without_the_plus_one(orc):
+    """The +1 of the recurrence is the derivative of the added point: for
+    the Mandelbulb the point is both the start and the constant.  Without it
+    dr would be prod n r_k^(n-1), the derivative of the map with c held
+    fixed.  On the axis with n = 2, one body from y0: dr = 2 y0 + 1 (with),
+    against 2 y0 (without)."""
+    ys = np.linspace(0.05, 1.3, 26)
+    fr = W.bulb(2.0, 1)
+    _, _, _, dr = orc.de(fr, np.stack([np.zeros_like(ys), ys, np.zeros_like(ys)], 1))
+    np.testing.assert_allclose(dr, 2.0 * ys + 1.0, rtol=1e-14)
+
+
+# ---------------------------------------------------------- rounding probes
+@pytest.mark.parametrize("rel", [2.0 ** -20, 1e-3, 0.25])
+def test_probe_noise_is_uniform_on_the_stated_interval(orc, rel):
+    """The probes' factor is uniform on [1 - rel, 1 + rel]: range, mean,
+    variance rel^2/3, a Kolmogorov-Smirnov test, and no correlation between
+    neighbouring components, bodies and points."""
+    from scipy import stats as sst
+    keys = [(s, p, b, c) for s in (1000, 1003) for p in range(40) for b in range(5) for c in range(4)]
+    v = np.array([orc.probe_noise(s, p, b, c, rel) for s, p, b, c in keys])
+    assert v.min() >= 1.0 - rel and v.max() <= 1.0 + rel
+    u = (v - (1.0 - rel)) / (2.0 * rel)
+    N = u.size
+    assert abs(u.mean() - 0.5) < 4.0 * math.sqrt(1.0 / 12.0 / N)
+    assert abs(u.var() - 1.0 / 12.0) < 0.1 / 12.0
+    assert sst.kstest(u, "uniform").pvalue > 1e-3
+    grid = u.reshape(2, 40, 5, 4)
+    for ax in (1, 2, 3):
+        a = np.moveaxis(grid, ax, -1)
+        r = np.corrcoef(a[..., :-1].ravel(), a[..., 1:].ravel())[0, 1]
+        assert abs(r) < 0.1, (ax, r)
+    # same key, same draw; another seed, another draw
+    assert orc.probe_noise(7, 3, 2, 1, rel) == orc.probe_noise(7, 3, 2, 1, rel)
+    assert orc.probe_noise(7, 3, 2, 1, rel) != orc.probe_noise(8, 3, 2, 1, rel)
+
+
+@pytest.mark.parametrize("kind", ["julia", "cubic", "bulb8", "bulb_real"])
+@pytest.mark.parametrize("mode", ["tetra", "central", "analytic"])
+def test_probes_at_zero_perturbation_are_the_plain_functions(orc, kind, mode):
+    """With rel = 0 every factor is exactly 1, so the perturbed normal and
+    trap must reproduce normal_at and orbit_trap bit for bit; and as rel
+    shrinks the perturbed normal must converge to the plain one."""
+    fr = {"julia": W.julia([-0.2, 0.6, 0.2, 0.2], max_iter=11), "cubic": W.julia([-0.45, 0.1, 0.4, 0.2], 10, degree=3),
+          "bulb8": W.bulb(8.0, 10), "bulb_real": W.bulb(6.37, 10)}[kind]
+    rng = np.random.default_rng(17)
+    pts = rng.normal(size=(300, 3))
+    pts *= (rng.uniform(0.6, 1.3, size=(300, 1)) / np.linalg.norm(pts, axis=1, keepdims=True))
+    dirs = -pts / np.linalg.norm(pts, axis=1, keepdims=True)
+    eps = np.full(300, 1e-3)
+    ref = orc.normal_at(fr, pts, dirs, eps, mode)
+    np.testing.assert_array_equal(orc.normal_perturbed(fr, pts, dirs, eps, mode, 0.0, 1234), ref)
+    np.testing.assert_array_equal(orc.orbit_trap_perturbed(fr, pts, 0.0, 1234), orc.orbit_trap(fr, pts))
+    from parity import angle
+    prev = None
+    for rel in (1e-6, 1e-9, 1e-12):
+        a = np.median(angle(orc.normal_perturbed(fr, pts, dirs, eps, mode, rel, 99), ref))
+        if prev is not None:
+            assert a <= prev * 0.1 + 1e-15, (rel, a, prev)
+        prev = a
+    assert prev < 1e-6
