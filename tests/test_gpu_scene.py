@@ -244,7 +244,8 @@ def test_sixteen_object_scene(frt, orc):
     st = compare_scene(orc, sc, g, o, nd)
     print(st)
     assert len(set(o["object_id"][o["object_id"] >= 0].tolist())) == 16
-    assert_scene_parity(st)
+    # sixteen small objects at 160 x 120: many pixels border another object
+    assert_scene_parity(st, max_boundary=0.25, max_normal_boundary=0.20)
 
 
 def test_scene_workspace_too_small(frt):
