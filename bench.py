@@ -191,6 +191,43 @@ def adjoint_leg(frt, dev, reps):
             "rel_err_target": 1e-3}
 
 
+def batch_leg(frt, dev, reps):
+    """The batched-launch target: the 64 uneven Julia renders of the batch
+    workload (seeded c, cut plane, resolution, iterations and eps) launched
+    one by one (frt_render, one stream, one workspace), as one batch
+    (frt_render_batch) and as a replayed HIP graph of that batch; times from
+    events on the current stream, speedups over one by one."""
+    import torch
+
+    import workloads as W
+
+    jobs = W.julia_batch()
+    frames = [frt.alloc_frame(j, dev) for j in jobs]
+    ws = frt.alloc_workspace(len(jobs), dev)
+    ws1 = frt.alloc_workspace(1, dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        e.synchronize()
+        return s.elapsed_time(e) / reps
+
+    t_one = timed(lambda: [frt.render(j, dev, out=f, workspace=ws1) for j, f in zip(jobs, frames)])
+    t_batch = timed(lambda: frt.render_batch(jobs, dev, outs=frames, workspace=ws))
+    t_graph = timed(lambda: frt.render_batch(jobs, dev, outs=frames, workspace=ws, use_graph=True))
+    frt.graph_reset()
+    rays = sum(j["camera"]["width"] * j["camera"]["height"] for j in jobs)
+    return {"workload": "julia_batch_64_uneven", "renders": len(jobs), "rays": rays,
+            "one_by_one_ms": t_one, "batched_ms": t_batch, "graph_ms": t_graph,
+            "speedup": t_one / t_batch, "speedup_graph": t_one / t_graph,
+            "batched_mrays_per_s": rays / (t_batch * 1e-3) / 1e6, "target_speedup": 2.0}
+
+
 def hardware_fp32(flop, launch_ms):
     """FP32 FLOP the dominant kernel issues on active lanes per launch (rocprofv3
     SQ_INSTS_VALU_FLOPS_FP32 x 64 x VALUUtilization, from the profile of the
@@ -223,6 +260,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-ceilings", action="store_true", help="skip the vector-unit rate probes")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch leg")
     ap.add_argument("--tune", action="store_true",
                     help="re-run the autotuner on this workload before timing (default: the recorded tuned.json)")
     ap.add_argument("--workload", choices=["bulb_views", "stress"], default="bulb_views",
@@ -368,6 +406,8 @@ def main():
         rec["roofline"].update(measured_ceilings(frt, dev, achieved))
     if not args.no_adjoint and args.workload == "bulb_views":
         rec["adjoint"] = adjoint_leg(frt, dev, max(3, args.steps // 4))
+    if not args.no_batch and args.workload == "bulb_views":
+        rec["batch"] = batch_leg(frt, dev, max(3, args.steps // 4))
     if not args.no_cpu_baseline and args.workload == "bulb_views":
         rec["cpu_baseline"] = cpu_baseline(jobs, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

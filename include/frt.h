@@ -200,6 +200,7 @@ frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_
 frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace, size_t ws_bytes,
                             int32_t use_graph, void* stream);
 
+
 /* Adjoint of a batch render (the gradient the renderer is differentiated
  * for, by implicit differentiation at the hit points; Sec. 2 gives the
  * orbit-derivative estimate d whose root the depth is):
@@ -314,9 +315,11 @@ frt_status frt_math_eval(int32_t func, const float* x, const float* y, float* ou
  * kernels are measured against (the kernels are bound by the vector unit).
  * op: 0 FMA, 1 exp2, 2 log2, 3 1/sqrt, 4 1/x, 5 sqrt, 6 sin(2 pi x),
  * 7 a mix of four dependent FMAs per exp2 (whether transcendentals overlap
- * FMAs).  Each lane of 8 workgroups of 256 threads per compute unit runs
- * eight independent chains for iters rounds, iters in [1, 1 << 20]; op 7
- * counts five operations per chain and round.  *lane_ops_per_s receives
+ * FMAs), 8 FP32 add, 9 FP32 multiply, 10 an integer shift and add (the
+ * rate of non-FP32 vector instructions).  Each lane of 8 workgroups of 256
+ * threads per compute unit runs eight independent chains for iters rounds,
+ * iters in [1, 1 << 20]; op 7 counts five operations per chain and round,
+ * op 10 two.  *lane_ops_per_s receives
  * the lane operations per second of one timed launch (after one untimed
  * launch); an FMA is one operation (two FLOP).  Allocates and frees a
  * device buffer of 1 KiB per workgroup and waits for the launches on

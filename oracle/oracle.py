@@ -72,7 +72,9 @@ def lib():
     """Load liboracle.so, building it first when it is absent."""
     global _lib
     if _lib is None:
-        path = build_oracle.LIB
+        # FRT_ORACLE_LIB selects another build of the same source (the
+        # sanitised build of the CPU checks)
+        path = os.environ.get("FRT_ORACLE_LIB") or build_oracle.LIB
         if not os.path.exists(path):
             build_oracle.build()
         L = ctypes.CDLL(path)

@@ -15,7 +15,9 @@ import os
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libfrt.so")
+# FRT_LIB_PATH selects another build of the same sources (the host-sanitised
+# build of the CPU checks); by default the in-tree libfrt.so
+LIB_PATH = os.environ.get("FRT_LIB_PATH") or os.path.join(_PKG, "libfrt.so")
 
 FRT_OK, FRT_EINVAL, FRT_EHIP, FRT_ENOMEM, FRT_EUNSUPPORTED = 0, -1, -2, -3, -4
 STATUS_MISS_BOUNDS, STATUS_MISS_TMAX, STATUS_HIT, STATUS_HIT_CUT, STATUS_HIT_EXHAUSTED = 0, 1, 2, 3, 4
@@ -376,7 +378,8 @@ def math_eval(func, x, y=None, device="cuda"):
     return out
 
 
-RATE_OPS = {"fma": 0, "exp2": 1, "log2": 2, "rsq": 3, "rcp": 4, "sqrt": 5, "sin_rev": 6, "fma4_exp2": 7}
+RATE_OPS = {"fma": 0, "exp2": 1, "log2": 2, "rsq": 3, "rcp": 4, "sqrt": 5, "sin_rev": 6, "fma4_exp2": 7,
+            "fadd": 8, "fmul": 9, "int_shift_add": 10}
 
 
 def valu_rate(op, iters, device="cuda"):

@@ -26,10 +26,19 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer for the CPU
+# checks of the host code (argument validation, packing, layout); the device
+# code is built as usual.
+SANITIZE_HOST = "-O1 -g -Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined " \
+                "-Xarch_host -fno-sanitize-recover=undefined -Xarch_host -fno-omit-frame-pointer -shared-libsan"
+
+
+def build(verbose: bool = False, sanitize: bool = False, out: str = None) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+    dest = out or LIB
+    tmp = dest + ".tmp"
+    opt = SANITIZE_HOST.split() if sanitize else ["-O3"]
+    cmd = [hipcc(), "--offload-arch=" + ARCH] + opt + ["-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-I", INCLUDE, "-I", CSRC] + srcs + ["-o", tmp]
     if verbose:
@@ -40,8 +49,8 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + out)
     if verbose and out.strip():
         print(out, flush=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, dest)
+    return dest
 
 
 if __name__ == "__main__":

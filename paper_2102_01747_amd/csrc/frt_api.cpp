@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -89,15 +90,20 @@ bool occupancy(const void* kernel, int block, int& per_cu, std::string& why) {
         int device;
         int per_cu;
     };
+    // a fixed table: (kernel symbols x 4 block sizes x devices in use) stays
+    // far below its size; when full, queries are simply not cached
     static std::mutex occ_mu;
-    static std::vector<OccEntry> occ_cache;
+    static OccEntry occ_cache[256];
+    static int occ_n = 0;
     int dev = 0;
     (void)hipGetDevice(&dev);
     per_cu = 0;
     {
         std::lock_guard<std::mutex> lk(occ_mu);
-        for (const OccEntry& o : occ_cache)
+        for (int i = 0; i < occ_n; ++i) {
+            const OccEntry& o = occ_cache[i];
             if (o.kernel == kernel && o.block == block && o.device == dev) per_cu = o.per_cu;
+        }
     }
     if (per_cu > 0) return true;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
@@ -106,7 +112,7 @@ bool occupancy(const void* kernel, int block, int& per_cu, std::string& why) {
         return false;
     }
     std::lock_guard<std::mutex> lk(occ_mu);
-    occ_cache.push_back(OccEntry{kernel, block, dev, per_cu});
+    if (occ_n < 256) occ_cache[occ_n++] = OccEntry{kernel, block, dev, per_cu};
     return true;
 }
 
@@ -225,6 +231,27 @@ bool validate(const frt_camera* cam, const frt_fractal* fr, const frt_plane* pla
 // --------------------------------------------------------------- packing
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// The integer power a kernel variant may use: the Julia degree, an integral
+// Mandelbulb n in [2, 64], or 0 (real n).
+int int_power_of(const frt_fractal* fr) {
+    if (fr->kind == FRT_JULIA) return int(fr->power);
+    const float ip = std::floor(fr->power);
+    return (ip == fr->power && ip >= 2.0f && ip <= 64.0f) ? int(ip) : 0;
+}
+
+int variant_of_frac(const frt_fractal* fr) {
+    const int ip = int_power_of(fr);
+    if (fr->kind == FRT_JULIA) return ip == 2 ? frt::kVarJulia : frt::kVarJuliaDeg;
+    if (ip == 8) return frt::kVarBulb8;
+    return ip > 0 ? frt::kVarBulbInt : frt::kVarBulbReal;
+}
+
+// Rays of one render in the ray index space: whole 8x8 tiles.
+int64_t ray_count_of(const frt_camera* cam) {
+    const int64_t tx = (cam->width + frt::kTile - 1) / frt::kTile, ty = (cam->height + frt::kTile - 1) / frt::kTile;
+    return tx * ty * frt::kRaysPerTile;
+}
+
 void pack(const frt_camera* cam, const frt_fractal* fr, const frt_plane* planes, int32_t n_planes,
           const frt_march* mc, const frt_frame& out, int64_t ray_begin, JobDev& J) {
     std::memset(&J, 0, sizeof(J));
@@ -266,7 +293,7 @@ void pack(const frt_camera* cam, const frt_fractal* fr, const frt_plane* planes,
     double R;
     if (fr->kind == FRT_JULIA) {
         // degree p: the escape radius is the root R >= 1 of R^p - R - |c|
-        const int p = int(fr->power);
+        const int p = int_power_of(fr);
         J.power = float(p);
         J.int_power = p;
         const double cn = std::sqrt(double(fr->c[0]) * fr->c[0] + double(fr->c[1]) * fr->c[1] +
@@ -287,8 +314,7 @@ void pack(const frt_camera* cam, const frt_fractal* fr, const frt_plane* planes,
     } else {
         J.power = fr->power;
         R = std::pow(2.0, 1.0 / (double(fr->power) - 1.0));
-        const float ip = std::floor(fr->power);
-        J.int_power = (ip == fr->power && ip >= 2.0f && ip <= 64.0f) ? int(ip) : 0;
+        J.int_power = int_power_of(fr);
     }
     R = std::max(R, double(fr->bound_radius));
     J.radius = float(R);
@@ -328,7 +354,7 @@ void pack(const frt_camera* cam, const frt_fractal* fr, const frt_plane* planes,
     J.counters = out.counters;
     J.npix = int64_t(cam->width) * cam->height;
     J.ray_begin = ray_begin;
-    J.ray_count = int64_t(J.tiles_x) * J.tiles_y * frt::kRaysPerTile;
+    J.ray_count = ray_count_of(cam);
 }
 
 int variant_of(const JobDev& J) {
@@ -338,14 +364,19 @@ int variant_of(const JobDev& J) {
 }
 
 // ----------------------------------------------------- staging and graphs
+// Pinned host buffers for the job-table uploads, used in turn: a call waits
+// only when the upload of the call kStageSlots calls before it (which used
+// the same buffer) has not been copied yet.
 struct Staging {
     void* host = nullptr;
     size_t bytes = 0;
     hipEvent_t done = nullptr;   // recorded after the last upload from `host`
     bool pending = false;
 };
+constexpr int kStageSlots = 8;
 std::mutex g_stage_mu;
-Staging g_stage;
+Staging g_stage[kStageSlots];
+int g_stage_next = 0;
 
 struct GraphEntry {
     void* workspace;
@@ -369,41 +400,43 @@ std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;
 hipStream_t g_capture_stream = nullptr;
 
-// Copy consecutive host blocks into the start of the workspace through one
-// pinned staging buffer (reused; a new upload waits for the previous copy).
+// Copy consecutive host blocks into the start of the workspace through the
+// next pinned staging buffer of the ring.
 frt_status upload_parts(const void* const* parts, const size_t* sizes, int n_parts, void* workspace,
                         hipStream_t stream) {
     size_t bytes = 0;
     for (int i = 0; i < n_parts; ++i) bytes += sizes[i];
     std::lock_guard<std::mutex> lk(g_stage_mu);
+    Staging& sg = g_stage[g_stage_next];
+    g_stage_next = (g_stage_next + 1) % kStageSlots;
     hipError_t e;
-    if (g_stage.pending) {
-        e = hipEventSynchronize(g_stage.done);
+    if (sg.pending) {
+        e = hipEventSynchronize(sg.done);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-        g_stage.pending = false;
+        sg.pending = false;
     }
-    if (g_stage.bytes < bytes) {
-        if (g_stage.host) (void)hipHostFree(g_stage.host);
-        g_stage.host = nullptr;
-        g_stage.bytes = 0;
-        e = hipHostMalloc(&g_stage.host, bytes, hipHostMallocDefault);
+    if (sg.bytes < bytes) {
+        if (sg.host) (void)hipHostFree(sg.host);
+        sg.host = nullptr;
+        sg.bytes = 0;
+        e = hipHostMalloc(&sg.host, bytes, hipHostMallocDefault);
         if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
-        g_stage.bytes = bytes;
+        sg.bytes = bytes;
     }
-    if (!g_stage.done) {
-        e = hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming);
+    if (!sg.done) {
+        e = hipEventCreateWithFlags(&sg.done, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     }
     size_t off = 0;
     for (int i = 0; i < n_parts; ++i) {
-        if (sizes[i]) std::memcpy(static_cast<char*>(g_stage.host) + off, parts[i], sizes[i]);
+        if (sizes[i]) std::memcpy(static_cast<char*>(sg.host) + off, parts[i], sizes[i]);
         off += sizes[i];
     }
-    e = hipMemcpyAsync(workspace, g_stage.host, bytes, hipMemcpyHostToDevice, stream);
+    e = hipMemcpyAsync(workspace, sg.host, bytes, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-    e = hipEventRecord(g_stage.done, stream);
+    e = hipEventRecord(sg.done, stream);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    g_stage.pending = true;
+    sg.pending = true;
     return FRT_OK;
 }
 
@@ -424,6 +457,64 @@ frt_status check_workspace(void* workspace, size_t ws_bytes, int32_t n_jobs) {
 }
 
 }  // namespace
+
+namespace frt {
+
+void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+
+frt_status record_error(frt_status s, const char* msg) { return fail(s, msg ? msg : ""); }
+
+frt_status batch_validate(const frt_job* jobs, int32_t n_jobs) {
+    for (int i = 0; i < n_jobs; ++i) {
+        std::string why;
+        const frt_job& jb = jobs[i];
+        if (!validate(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, &jb.out, true, why))
+            return fail(FRT_EINVAL, "job " + std::to_string(i) + ": " + why);
+        if (jb.march.shading != FRT_SHADING_LAMBERT)
+            return fail(FRT_EUNSUPPORTED,
+                        "job " + std::to_string(i) + ": the closest-hit shading model is rendered by frt_render_scene");
+    }
+    return FRT_OK;
+}
+
+frt_status batch_layout(const frt_job* jobs, int32_t n_jobs, WorkspaceHeader& hdr, TraceGroup* groups, int& n_groups,
+                        bool (*sink)(void* ctx, const JobDev& J), void* ctx) {
+    n_groups = 0;
+    // every job is validated before anything is packed or launched
+    frt_status vs = batch_validate(jobs, n_jobs);
+    if (vs != FRT_OK) return vs;
+    // lay the rays out variant by variant: group v is one contiguous range of
+    // the ray index space traced by its own kernels (the table order is
+    // internal; outputs travel with each job)
+    std::memset(&hdr, 0, sizeof(hdr));
+    int64_t begin = 0;
+    for (int v = 0; v < kNumVariants; ++v) {
+        const int64_t g0 = begin;
+        bool shadow = false;
+        for (int i = 0; i < n_jobs; ++i) {
+            const frt_job& jb = jobs[i];
+            if (variant_of_frac(&jb.frac) != v) continue;
+            JobDev J;
+            pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, begin, J);
+            begin += J.ray_count;
+            shadow = shadow || J.shadow != 0;
+            if (!sink(ctx, J)) return fail(FRT_EHIP, "job table upload failed");
+        }
+        hdr.range[v][0] = static_cast<unsigned long long>(g0);
+        hdr.range[v][1] = static_cast<unsigned long long>(begin);
+        if (begin == g0) continue;
+        TraceGroup& g = groups[n_groups++];
+        g.variant = v;
+        g.any_shadow = shadow;
+        std::string why;
+        if (!make_cfg(trace_kernel_symbol(v, true), v, begin - g0, g.cfg, why)) return fail(FRT_EHIP, why);
+    }
+    hdr.total_rays = static_cast<unsigned long long>(begin);
+    hdr.n_jobs = n_jobs;
+    return FRT_OK;
+}
+
+}  // namespace frt
 
 // ======================================================================
 extern "C" {
@@ -534,57 +625,23 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
     if (use_graph != 0 && use_graph != 1) return fail(FRT_EINVAL, "use_graph must be 0 or 1");
     frt_status s = check_workspace(workspace, ws_bytes, n_jobs);
     if (s != FRT_OK) return s;
-    // pack every job, then lay the rays out variant by variant: group v is
-    // one contiguous range of the ray index space traced by its own kernels
-    // (the table order is internal; outputs travel with each job)
-    std::vector<JobDev> packed(static_cast<size_t>(n_jobs));
-    std::vector<int> var_of(static_cast<size_t>(n_jobs));
-    for (int i = 0; i < n_jobs; ++i) {
-        std::string why;
-        const frt_job& jb = jobs[i];
-        if (!validate(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, &jb.out, true, why))
-            return fail(FRT_EINVAL, "job " + std::to_string(i) + ": " + why);
-        if (jb.march.shading != FRT_SHADING_LAMBERT)
-            return fail(FRT_EUNSUPPORTED,
-                        "job " + std::to_string(i) + ": the closest-hit shading model is rendered by frt_render_scene");
-        pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, 0, packed[size_t(i)]);
-        var_of[size_t(i)] = variant_of(packed[size_t(i)]);
-    }
     WorkspaceHeader hdr;
-    std::memset(&hdr, 0, sizeof(hdr));
     std::vector<JobDev> table;
     table.reserve(size_t(n_jobs));
-    std::vector<frt::TraceGroup> groups;
-    int64_t begin = 0;
-    for (int v = 0; v < frt::kNumVariants; ++v) {
-        const int64_t g0 = begin;
-        bool shadow = false;
-        for (int i = 0; i < n_jobs; ++i) {
-            if (var_of[size_t(i)] != v) continue;
-            JobDev J = packed[size_t(i)];
-            J.ray_begin = begin;
-            begin += J.ray_count;
-            shadow = shadow || J.shadow != 0;
-            table.push_back(J);
-        }
-        hdr.range[v][0] = static_cast<unsigned long long>(g0);
-        hdr.range[v][1] = static_cast<unsigned long long>(begin);
-        if (begin == g0) continue;
-        frt::TraceGroup g;
-        g.variant = v;
-        g.any_shadow = shadow;
-        std::string why;
-        if (!make_cfg(frt::trace_kernel_symbol(v, true), v, begin - g0, g.cfg, why)) return fail(FRT_EHIP, why);
-        groups.push_back(g);
-    }
-    hdr.total_rays = static_cast<unsigned long long>(begin);
-    hdr.n_jobs = n_jobs;
+    frt::TraceGroup group_arr[frt::kNumVariants];
+    int ng = 0;
+    auto push = [](void* ctx, const JobDev& J) {
+        static_cast<std::vector<JobDev>*>(ctx)->push_back(J);
+        return true;
+    };
+    s = frt::batch_layout(jobs, n_jobs, hdr, group_arr, ng, push, &table);
+    if (s != FRT_OK) return s;
+    std::vector<frt::TraceGroup> groups(group_arr, group_arr + ng);
     hipStream_t st = static_cast<hipStream_t>(stream);
     s = upload_table(table, hdr, workspace, st);
     if (s != FRT_OK) return s;
     const JobDev* dev_jobs = reinterpret_cast<const JobDev*>(static_cast<char*>(workspace) + sizeof(WorkspaceHeader));
     WorkspaceHeader* dhdr = static_cast<WorkspaceHeader*>(workspace);
-    const int ng = static_cast<int>(groups.size());
     if (!use_graph) {
         hipError_t e = frt::launch_trace(groups.data(), ng, true, dev_jobs, table[0], dhdr, st, timing_marks());
         if (e != hipSuccess) return hip_fail(e, "trace launch");
@@ -705,7 +762,7 @@ frt_status frt_math_eval(int32_t func, const float* x, const float* y, float* ou
 
 frt_status frt_valu_rate(int32_t op, int32_t iters, double* lane_ops_per_s, void* stream) {
     g_last_error.clear();
-    if (op < 0 || op >= frt::kNumRateOps) return fail(FRT_EINVAL, "op must be in [0, 7]");
+    if (op < 0 || op >= frt::kNumRateOps) return fail(FRT_EINVAL, "op must be in [0, 10]");
     if (iters < 1 || iters > (1 << 20)) return fail(FRT_EINVAL, "iters must be in [1, 1 << 20]");
     if (!lane_ops_per_s) return fail(FRT_EINVAL, "null output");
     int dev = 0, cus = 0;

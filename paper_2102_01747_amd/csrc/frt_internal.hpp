@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "frt.h"
 #include "frt_job.hpp"
 
 namespace frt {
@@ -35,6 +36,21 @@ hipError_t launch_trace(const TraceGroup* groups, int n_groups, bool batch, cons
                         WorkspaceHeader* hdr, hipStream_t stream, hipEvent_t* marks = nullptr);
 const void* trace_kernel_symbol(int variant, bool batch);
 
+// Batch set-up shared by the batch entry points (frt_api.cpp): validates
+// every job before anything is packed, then packs the jobs variant by
+// variant (the order of the ray index space) and hands each JobDev, in
+// table order, to sink(ctx, J) (false aborts with FRT_EHIP); fills the
+// header's ranges, ray total and job count (the claim counters stay zero)
+// and one launch group per variant present (groups holds kNumVariants).
+// Errors are recorded for frt_last_error().
+frt_status batch_layout(const frt_job* jobs, int32_t n_jobs, WorkspaceHeader& hdr, TraceGroup* groups, int& n_groups,
+                        bool (*sink)(void* ctx, const JobDev& J), void* ctx);
+// The validation pass of batch_layout alone (host only, no device call).
+frt_status batch_validate(const frt_job* jobs, int32_t n_jobs);
+// frt_last_error() bookkeeping for entry points outside frt_api.cpp.
+void set_last_error(const char* msg);
+frt_status record_error(frt_status s, const char* msg);
+
 // Point queries (frt_query.hip).
 struct OrbitParams;
 hipError_t launch_distance(int variant, const OrbitParams& P, const float* pts, long long n, float* d, int* it,
@@ -52,7 +68,10 @@ hipError_t launch_math(int func, const float* x, const float* y, float* out, lon
 // Issue-rate probes of the vector unit (frt_rates.hip): `blocks` workgroups
 // of kRateBlock threads, each lane running `iters` rounds of
 // rate_ops_per_iter(op) lane operations; sink holds one float per thread.
-enum RateOp { kRateFma = 0, kRateExp2, kRateLog2, kRateRsq, kRateRcp, kRateSqrt, kRateSin, kRateMix, kNumRateOps };
+enum RateOp {
+    kRateFma = 0, kRateExp2, kRateLog2, kRateRsq, kRateRcp, kRateSqrt, kRateSin, kRateMix,
+    kRateFAdd, kRateFMul, kRateIntShiftAdd, kNumRateOps
+};
 constexpr int kRateBlock = 256;
 int rate_ops_per_iter(int op);
 hipError_t launch_rate(int op, int iters, float* sink, int blocks, hipStream_t stream);

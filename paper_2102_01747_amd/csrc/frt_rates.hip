@@ -30,7 +30,13 @@ __device__ __forceinline__ float link(float v, float a, float b) {
     else if constexpr (OP == kRateRsq) return hw_rsq(fabsf(v));
     else if constexpr (OP == kRateRcp) return hw_rcp(v);
     else if constexpr (OP == kRateSqrt) return hw_sqrt(fabsf(v));
-    else return hw_sin_rev(v);
+    else if constexpr (OP == kRateFAdd) return v + b;
+    else if constexpr (OP == kRateFMul) return v * a;
+    else if constexpr (OP == kRateIntShiftAdd) {
+        // two integer operations (shift, add) on the bits of the chain
+        const unsigned u = __float_as_uint(v);
+        return __uint_as_float(u + (u >> 3));
+    } else return hw_sin_rev(v);
 }
 
 template <int OP>
@@ -65,7 +71,9 @@ __global__ __launch_bounds__(256) void rate_kernel(float* __restrict__ sink, int
 
 }  // namespace
 
-int rate_ops_per_iter(int op) { return op == kRateMix ? 5 * kChains : kChains; }
+int rate_ops_per_iter(int op) {
+    return op == kRateMix ? 5 * kChains : op == kRateIntShiftAdd ? 2 * kChains : kChains;
+}
 
 hipError_t launch_rate(int op, int iters, float* sink, int blocks, hipStream_t stream) {
     // a and b keep the FMA chains bounded (|a| < 1) and unknown to the compiler
@@ -79,6 +87,11 @@ hipError_t launch_rate(int op, int iters, float* sink, int blocks, hipStream_t s
         case kRateRcp: hipLaunchKernelGGL(rate_kernel<kRateRcp>, grid, block, 0, stream, sink, iters, a, b); break;
         case kRateSqrt: hipLaunchKernelGGL(rate_kernel<kRateSqrt>, grid, block, 0, stream, sink, iters, a, b); break;
         case kRateSin: hipLaunchKernelGGL(rate_kernel<kRateSin>, grid, block, 0, stream, sink, iters, a, b); break;
+        case kRateFAdd: hipLaunchKernelGGL(rate_kernel<kRateFAdd>, grid, block, 0, stream, sink, iters, a, b); break;
+        case kRateFMul: hipLaunchKernelGGL(rate_kernel<kRateFMul>, grid, block, 0, stream, sink, iters, a, b); break;
+        case kRateIntShiftAdd:
+            hipLaunchKernelGGL(rate_kernel<kRateIntShiftAdd>, grid, block, 0, stream, sink, iters, a, b);
+            break;
         default: hipLaunchKernelGGL(rate_kernel<kRateMix>, grid, block, 0, stream, sink, iters, a, b); break;
     }
     return hipGetLastError();

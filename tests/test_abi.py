@@ -59,7 +59,8 @@ def test_host_only_calls_without_gpu():
     assert b"n_objects" in L.frt_last_error()
     # the rate probe checks its arguments before it asks for a device
     r = ctypes.c_double()
-    assert L.frt_valu_rate(8, 16, ctypes.byref(r), None) == frt.FRT_EINVAL
+    assert L.frt_valu_rate(11, 16, ctypes.byref(r), None) == frt.FRT_EINVAL
+    assert L.frt_valu_rate(-1, 16, ctypes.byref(r), None) == frt.FRT_EINVAL
     assert L.frt_valu_rate(0, 0, ctypes.byref(r), None) == frt.FRT_EINVAL
     assert L.frt_valu_rate(0, (1 << 20) + 1, ctypes.byref(r), None) == frt.FRT_EINVAL
     assert L.frt_valu_rate(0, 16, None, None) == frt.FRT_EINVAL

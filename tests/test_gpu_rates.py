@@ -43,3 +43,14 @@ def test_mix_of_fma_and_exp2(frt):
           % (measured, serial, overlap))
     assert 0.8 * overlap < measured < 1.25 * serial
 
+
+
+@pytest.mark.parametrize("op", ["fadd", "fmul", "int_shift_add"])
+def test_other_vector_op_rates(frt, op):
+    """FP32 add and multiply, and integer shift-and-add chains: the issue
+    rate of the non-FMA instructions that make up the rest of the march
+    kernels' vector work, against the FMA rate."""
+    fma = frt.valu_rate("fma", 16384)
+    r = frt.valu_rate(op, 8192)
+    print("%s: %.2f T lane-ops/s, %.3f of the FMA rate" % (op, r / 1e12, r / fma))
+    assert 0.3 * fma < r < 4.0 * fma
