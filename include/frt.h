@@ -200,6 +200,25 @@ frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_
 frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace, size_t ws_bytes,
                             int32_t use_graph, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * render as frt_render_batch with use_graph = 0 (same kernels, bit-identical
+ * output), but its workspace is the library's own device scratch, a
+ * file-scope device array of frt_noalloc_scratch_bytes() bytes (about
+ * 140 KiB) that each GPU the library runs on holds until the process ends.
+ * The call allocates nothing: no hipMalloc/hipFree, no pinned staging (the
+ * job table travels in the arguments of small upload kernels), no events, no
+ * graphs; it records no stage timing.  The caller still owns the output
+ * planes named in jobs[i].out.
+ * jobs: host array of n_jobs entries, 1 <= n_jobs <= FRT_NOALLOC_MAX_JOBS.
+ * Every call on one GPU shares that GPU's scratch, which keeps the last
+ * call's contents (the claim counters are cleared by each call's own
+ * kernels): calls that overlap on one GPU -- on different streams, or from
+ * different host threads without ordering -- race and must not be issued.
+ * Errors as frt_render_batch; FRT_EINVAL also for n_jobs above the maximum. */
+#define FRT_NOALLOC_MAX_JOBS 256
+frt_status frt_render_batch_noalloc(const frt_job* jobs, int32_t n_jobs, void* stream);
+size_t frt_noalloc_scratch_bytes(void);
 
 /* Adjoint of a batch render (the gradient the renderer is differentiated
  * for, by implicit differentiation at the hit points; Sec. 2 gives the

@@ -90,6 +90,10 @@ def lib():
         L.frt_render.restype = ctypes.c_int
         L.frt_render_batch.argtypes = [P(Job), i32, vp, sz, i32, vp]
         L.frt_render_batch.restype = ctypes.c_int
+        L.frt_render_batch_noalloc.argtypes = [P(Job), i32, vp]
+        L.frt_render_batch_noalloc.restype = ctypes.c_int
+        L.frt_noalloc_scratch_bytes.argtypes = []
+        L.frt_noalloc_scratch_bytes.restype = sz
         L.frt_render_backward.argtypes = [P(Job), i32, P(vp), P(vp), P(vp), P(vp), vp, vp, vp, vp, sz, vp]
         L.frt_render_backward.restype = ctypes.c_int
         L.frt_autotune_set.argtypes = [i32, i32, i32, i32, i32, i32]
@@ -284,6 +288,24 @@ def render_batch(jobs, device="cuda", counters=False, use_graph=False, outs=None
     arr = (Job * len(jobs))(*[make_job(j, f) for j, f in zip(jobs, frames)])
     _check(L.frt_render_batch(arr, len(jobs), _ptr(ws), ws.numel(), int(bool(use_graph)), _stream(dev)))
     return frames
+
+
+NOALLOC_MAX_JOBS = 256   # FRT_NOALLOC_MAX_JOBS
+
+
+def render_batch_noalloc(jobs, outs, device="cuda"):
+    """render_batch into caller-allocated frames through the entry point
+    that allocates nothing (its workspace is the library's own device
+    scratch; calls that overlap on one GPU race)."""
+    L = lib()
+    dev = _device(device)
+    arr = (Job * len(jobs))(*[make_job(j, f) for j, f in zip(jobs, outs)])
+    _check(L.frt_render_batch_noalloc(arr, len(jobs), _stream(dev)))
+    return outs
+
+
+def noalloc_scratch_bytes():
+    return int(lib().frt_noalloc_scratch_bytes())
 
 
 def render_backward(jobs, frames, g_colour=None, g_depth=None, g_normal=None, device="cuda", workspace=None,

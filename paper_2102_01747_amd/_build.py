@@ -15,7 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfrt.so")
-SOURCES = ["frt_trace.hip", "frt_query.hip", "frt_adjoint.hip", "frt_scene.hip", "frt_rates.hip", "frt_api.cpp"]
+SOURCES = ["frt_trace.hip", "frt_query.hip", "frt_adjoint.hip", "frt_scene.hip", "frt_rates.hip", "frt_noalloc.hip",
+           "frt_api.cpp"]
 ARCH = os.environ.get("FRT_OFFLOAD_ARCH", "gfx950")
 
 

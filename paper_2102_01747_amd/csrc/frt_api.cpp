@@ -683,6 +683,71 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
     return FRT_OK;
 }
 
+size_t frt_noalloc_scratch_bytes(void) { return frt::noalloc_scratch_bytes(); }
+
+frt_status frt_render_batch_noalloc(const frt_job* jobs, int32_t n_jobs, void* stream) {
+    g_last_error.clear();
+    if (!jobs || n_jobs < 1) return fail(FRT_EINVAL, "jobs is null or n_jobs < 1");
+    if (n_jobs > FRT_NOALLOC_MAX_JOBS) return fail(FRT_EINVAL, "n_jobs exceeds FRT_NOALLOC_MAX_JOBS");
+    // every job is checked before the first device call
+    frt_status vs = frt::batch_validate(jobs, n_jobs);
+    if (vs != FRT_OK) return vs;
+    hipError_t he = hipSuccess;
+    char* ws = static_cast<char*>(frt::noalloc_scratch(he));
+    if (!ws) return hip_fail(he, "scratch address");
+    if (frt::noalloc_scratch_bytes() < frt_workspace_bytes(n_jobs)) return fail(FRT_ENOMEM, "scratch too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // the job table is written into the scratch through argument-carried
+    // uploads of a few jobs each, in table order, as the layout packs it
+    struct Sink {
+        hipStream_t st;
+        char* dst;
+        hipError_t err;
+        int fill;
+        JobDev first;
+        bool have_first;
+        alignas(16) unsigned char buf[frt::kUploadBytes];
+        bool flush() {
+            if (fill > 0) err = frt::launch_upload(dst, buf, fill, st);
+            dst += fill;
+            fill = 0;
+            return err == hipSuccess;
+        }
+    } sk;
+    sk.st = st;
+    sk.dst = ws + sizeof(WorkspaceHeader);
+    sk.err = hipSuccess;
+    sk.fill = 0;
+    sk.have_first = false;
+    static_assert(sizeof(JobDev) % 16 == 0 && sizeof(JobDev) <= frt::kUploadBytes, "job upload granularity");
+    auto put = [](void* ctx, const JobDev& J) {
+        Sink& k = *static_cast<Sink*>(ctx);
+        if (!k.have_first) {
+            k.first = J;
+            k.have_first = true;
+        }
+        if (k.fill + int(sizeof(JobDev)) > frt::kUploadBytes && !k.flush()) return false;
+        std::memcpy(k.buf + k.fill, &J, sizeof(JobDev));
+        k.fill += int(sizeof(JobDev));
+        return true;
+    };
+    WorkspaceHeader hdr;
+    frt::TraceGroup groups[frt::kNumVariants];
+    int ng = 0;
+    frt_status s = frt::batch_layout(jobs, n_jobs, hdr, groups, ng, put, &sk);
+    if (s != FRT_OK) return s;
+    if (!sk.flush()) return hip_fail(sk.err, "job table upload");
+    // the header's fields (its first KiB; the claim counters after them are
+    // zeroed by the trace launch's reset kernel)
+    static_assert(offsetof(WorkspaceHeader, queue) == 1024, "header fields fit one KiB");
+    hipError_t e = frt::launch_upload(ws, &hdr, 1024, st);
+    if (e != hipSuccess) return hip_fail(e, "header upload");
+    e = frt::launch_trace(groups, ng, true, reinterpret_cast<const JobDev*>(ws + sizeof(WorkspaceHeader)), sk.first,
+                          reinterpret_cast<WorkspaceHeader*>(ws), st, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "trace launch");
+    return FRT_OK;
+}
+
 // Orbit parameters and kernel variant of a fractal for the point queries
 // (validated with a placeholder camera and march).
 static bool query_params(const frt_fractal* frac, frt::OrbitParams& P, int& variant, std::string& why) {

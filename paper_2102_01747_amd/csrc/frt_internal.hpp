@@ -51,6 +51,16 @@ frt_status batch_validate(const frt_job* jobs, int32_t n_jobs);
 void set_last_error(const char* msg);
 frt_status record_error(frt_status s, const char* msg);
 
+// Writes `bytes` (a multiple of 16, at most kUploadBytes) from host memory
+// to the 16-byte aligned device address dst by a kernel that carries them in
+// its arguments: no staging buffer, nothing allocated (frt_noalloc.hip).
+constexpr int kUploadBytes = 3072;
+hipError_t launch_upload(void* dst, const void* src, int bytes, hipStream_t stream);
+// The library's own device scratch on the current device (file-scope
+// device array; its address is looked up once per device), and its size.
+void* noalloc_scratch(hipError_t& err);
+size_t noalloc_scratch_bytes();
+
 // Point queries (frt_query.hip).
 struct OrbitParams;
 hipError_t launch_distance(int variant, const OrbitParams& P, const float* pts, long long n, float* d, int* it,

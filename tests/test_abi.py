@@ -180,6 +180,15 @@ def test_batch_and_backward_validation_on_the_host():
     assert b"job 2" in L.frt_last_error() and b"max_iter" in L.frt_last_error()
     assert L.frt_render_batch(table([good]), 1, ws, 1 << 20, 2, None) == frt.FRT_EINVAL   # use_graph
     assert L.frt_render_batch(table([good]), 1, ws, 64, 0, None) == frt.FRT_ENOMEM
+    # the entry point that allocates nothing checks the same before any device call
+    assert L.frt_render_batch_noalloc(arr, 3, None) == frt.FRT_EINVAL
+    assert b"job 2" in L.frt_last_error() and b"max_iter" in L.frt_last_error()
+    assert L.frt_render_batch_noalloc(None, 1, None) == frt.FRT_EINVAL
+    assert L.frt_render_batch_noalloc(table([good]), 0, None) == frt.FRT_EINVAL
+    big = table([good] * (frt.NOALLOC_MAX_JOBS + 1))
+    assert L.frt_render_batch_noalloc(big, frt.NOALLOC_MAX_JOBS + 1, None) == frt.FRT_EINVAL
+    assert b"FRT_NOALLOC_MAX_JOBS" in L.frt_last_error()
+    assert frt.noalloc_scratch_bytes() == frt.workspace_bytes(frt.NOALLOC_MAX_JOBS) <= 256 << 10
 
     analytic = copy.deepcopy(good)
     analytic["march"]["normal_mode"] = "analytic"
