@@ -546,6 +546,19 @@ def _phong_spec(nrm, L, V, ndl, shininess):
     return np.where(ndl > 0.0, np.maximum(0.0, np.einsum("ij,ij->i", Rl, V)) ** shininess, 0.0)
 
 
+def shade_lambert(march, normals, shadowed):
+    """Lambert colour (R11) of hits with the given unit normals [n, 3] and
+    shadow outcomes [n] (bool): albedo (k_a + k_d max(0, N.L) V), as the
+    render computes it, for shading a normal evaluated at another point.
+    Returns [3, n]."""
+    L = np.array(march["light_dir"], dtype=np.float64)
+    L /= np.linalg.norm(L)
+    ndl = np.asarray(normals, np.float64) @ L
+    vis = np.where(np.asarray(shadowed, bool), 0.0, 1.0)
+    lam = march["k_ambient"] + march["k_diffuse"] * np.maximum(0.0, ndl) * vis
+    return np.array(march["albedo"], dtype=np.float64)[:, None] * lam[None, :]
+
+
 def probe_noise(seed, point, body, comp, rel):
     """The rounding probes' multiplicative factor for one (seed, point, body,
     component): uniform on [1 - rel, 1 + rel]."""
