@@ -205,15 +205,6 @@ __device__ __forceinline__ float bulb_rpow(float m) {
     else return ipow_c<K / 2 - 1>(m) * hw_sqrt(m);
 }
 
-// ((z + i x) / rho)^K, the azimuthal factor of the power map: a unit number,
-// except on the polar axis, where rho is floored and the factor it scales
-// (Im Y^K) vanishes; powers of two take the unit squaring.
-template <int K>
-__device__ __forceinline__ void zpow(float& re, float& im) {
-    if constexpr ((K & (K - 1)) == 0) cpow_unit_c<K>(re, im);
-    else cpow_c<K>(re, im);
-}
-
 template <int MODE>
 struct BulbOrbit {
     float wx, wy, wz, m, dr, px, py, pz;
@@ -253,7 +244,7 @@ struct BulbOrbit {
             if constexpr (MODE > 0) {
                 ndr = fmaf(static_cast<float>(MODE) * bulb_rpow<MODE>(m), dr, 1.0f);
                 cpow_c<MODE>(yr, yi);
-                zpow<MODE>(zr, zi);
+                cpow_c<MODE>(zr, zi);
             } else {
                 ndr = fmaf(P.n * ipow(hw_sqrt(m), P.ipow - 1), dr, 1.0f);
                 cpow_int(yr, yi, P.ipow);
@@ -302,7 +293,7 @@ struct BulbOrbit {
             if constexpr (MODE > 0) {
                 dr = fmaf(static_cast<float>(MODE) * bulb_rpow<MODE>(m), dr, 1.0f);
                 cpow_c<MODE>(yr, yi);
-                zpow<MODE>(zr, zi);
+                cpow_c<MODE>(zr, zi);
             } else {
                 dr = fmaf(P.n * ipow(hw_sqrt(m), P.ipow - 1), dr, 1.0f);
                 cpow_int(yr, yi, P.ipow);

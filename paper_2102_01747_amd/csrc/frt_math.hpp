@@ -107,23 +107,6 @@ __device__ __forceinline__ void cpow_c(float& re, float& im) {
     }
 }
 
-// (re + i im)^K for a unit complex number (re^2 + im^2 = 1): squaring is
-// (2 re^2 - 1, 2 re im), one operation fewer than for a general number.
-// The identity holds to the rounding of the input's modulus, which the
-// powers then carry as the general scheme does.
-template <int K>
-__device__ __forceinline__ void cpow_unit_c(float& re, float& im) {
-    static_assert((K & (K - 1)) == 0, "powers of two only");
-    if constexpr (K > 1) {
-        cpow_unit_c<K / 2>(re, im);
-        const float r2 = re + re;
-        const float sr = fmaf(r2, re, -1.0f);
-        const float si = r2 * im;
-        re = sr;
-        im = si;
-    }
-}
-
 // (re + i im)^k for integer k >= 1, same scheme as ipow
 __device__ __forceinline__ void cpow_int(float& re, float& im, int k) {
     const float br = re, bi = im;

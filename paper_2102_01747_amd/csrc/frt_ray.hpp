@@ -160,39 +160,4 @@ __device__ __forceinline__ bool ray_pixel(const JobDev* __restrict__ jobs, const
     return tile_pixel(J, g - J.ray_begin, px, py);
 }
 
-// ---------------------------------------------------------------------------
-// Hit refinement: the root of g(t) = d(o + t dir) - eps(t) on the final march
-// bracket [a, b], g(a) >= 0 > g(b), by the ITP method (interpolate, truncate,
-// project; Oliveira and Takahashi, 2020), down to a bracket of width tol.
-// Each point starts from the regula-falsi point, is moved toward the
-// midpoint by kap (b - a)^2 (kap = 0.05 / (b0 - a0)) so that both ends of the
-// bracket converge, and is kept within rs - (b - a) / 2 of the midpoint,
-// rs = tol 2^(n - j) after j points, n = ceil(log2((b0 - a0) / tol)): at
-// most one point more than bisection needs, and superlinear convergence
-// where g is smooth.  The caller halves rs after every point.
-// ---------------------------------------------------------------------------
-struct ItpState {
-    float kap, rs;
-};
-
-__device__ __forceinline__ ItpState itp_start(float a, float b, float tol) {
-    const float w = b - a;
-    int e;
-    const float f = frexpf(__fdividef(w, tol), &e);   // w / tol = f 2^e, f in [0.5, 1)
-    const int n = f == 0.5f ? e - 1 : e;               // ceil(log2(w / tol)), w > tol
-    return ItpState{__fdividef(0.05f, w), ldexpf(tol, n)};
-}
-
-__device__ __forceinline__ float itp_point(float a, float b, float ya, float yb, float kap, float rs) {
-    const float w = b - a;
-    const float xh = 0.5f * (a + b);
-    const float xf = fmaf(-yb, __fdividef(w, yb - ya), b);   // regula falsi
-    const float diff = xh - xf;
-    const float sg = diff >= 0.0f ? 1.0f : -1.0f;
-    const float delta = kap * w * w;
-    const float xt = delta <= fabsf(diff) ? fmaf(sg, delta, xf) : xh;
-    const float r = fmaxf(fmaf(-0.5f, w, rs), 0.0f);
-    return fabsf(xt - xh) <= r ? xt : fmaf(-sg, r, xh);
-}
-
 }  // namespace frt

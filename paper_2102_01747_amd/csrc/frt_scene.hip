@@ -12,7 +12,7 @@
 //
 // One lane per pixel (8x8 tiles, one wave a tile).  Each lane marches every
 // object in index order with the same rules as the persistent march kernel
-// (interval, cut face, Listing 3, ITP refinement to eps/32 and a secant step),
+// (interval, cut face, Listing 3, bisection to eps/32 and a secant step),
 // capping an object's range at the best world depth so far plus one full
 // step, so a later object can only replace the hit with a closer one (ties
 // keep the lower index).  The hit is shaded in world space; its shadow ray
@@ -32,7 +32,7 @@ namespace frt {
 
 namespace {
 
-constexpr float kSceneRefineTol = 1.0f / 32.0f;   // same bracket width and ITP points as the march kernel
+constexpr float kSceneRefineTol = 1.0f / 32.0f;   // same bracket width as the march kernel
 
 struct MarchOut {
     int status;      // class and flags
@@ -88,11 +88,8 @@ __device__ MarchOut march_object(const JobDev& J, const OrbitParams& P, float ox
             float t1 = t, gb = de.d - fmaf(er, t, ea);
             lh -= fmaf(er, lt, ea);
             int rk = 0;
-            const float tol = kSceneRefineTol * fmaf(er, t1, ea);
-            ItpState itp = itp_start(lt, t1, t1 - lt > tol ? tol : t1 - lt);
             while (rk < J.refine_iters && t1 - lt > kSceneRefineTol * fmaf(er, t1, ea)) {
-                const float tm = itp_point(lt, t1, lh, gb, itp.kap, itp.rs);
-                itp.rs *= 0.5f;
+                const float tm = 0.5f * (lt + t1);
                 de = de_once(orb, P, fmaf(tm, dx, ox), fmaf(tm, dy, oy), fmaf(tm, dz, oz));
                 r.evals += 1u;
                 r.bodies += static_cast<unsigned>(de.bodies);

@@ -6,7 +6,7 @@
 // this latency-bound loop needs):
 //   1. march_kernel<primary>: search interval (bounding sphere and cut
 //      planes), cut-face test, sphere-tracing march of Listing 3 and the
-//      ITP refinement of the hit (frt_ray.hpp); writes depth, status and counters
+//      bisection refinement of the hit; writes depth, status and counters
 //      (and the plane normal of cut-face hits, and the miss encoding);
 //   2. normal_kernel: normal taps of Eq. 5 / Listing 5 around each refined
 //      hit, the normal, and Lambert shading assuming the point is lit;
@@ -32,9 +32,10 @@
 
 namespace frt {
 
-// Refinement (ITP, frt_ray.hpp) stops once the root bracket is narrower than
-// eps(t) / 32, then takes one secant step on the final bracket.  A coarser
-// bracket keeps the depth within tolerance but moves the normal taps with it.
+// Bisection stops once the root bracket is narrower than eps(t) / 32 (then one
+// secant step on the final bracket).  A coarser bracket keeps the depth within
+// tolerance but moves the normal taps with it; the bisection also picks the
+// same root as the oracle's when a step holds several crossings.
 constexpr float kRefineTol = 1.0f / 32.0f;
 // Upper bound on orbit bodies per loop trip (keeps finished rays flowing).
 constexpr int kMaxBodiesPerTrip = 64;
@@ -168,7 +169,6 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
     unsigned evals = 0, bodies = 0;
     float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 1.f;
     float t = 0.f, t1 = 0.f, lt = 0.f, lh = 0.f, gb = 0.f, ea = 0.f, er = 0.f;
-    ItpState itp{0.f, 0.f};   // refinement: ITP weights of the current bracket
     // march settings of the lane's job, copied when the ray is claimed
     float clamp = 0.2f;
     int max_steps = 1, refine_iters = 0;
@@ -417,11 +417,9 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                             gb = d - fmaf(er, t, ea);
                             t1 = t;
                             rk = 0;
-                            const float tol = kRefineTol * fmaf(er, t1, ea);
-                            if (refine_iters > 0 && t1 - lt > tol) {
+                            if (refine_iters > 0 && t1 - lt > kRefineTol * fmaf(er, t1, ea)) {
                                 phase = kRefine;
-                                itp = itp_start(lt, t1, tol);
-                                t = itp_point(lt, t1, lh, gb, itp.kap, itp.rs);
+                                t = 0.5f * (lt + t1);
                             } else {
                                 t = fmaf(-gb, __fdividef(t1 - lt, gb - lh), t1);   // secant on the bracket
                                 phase = kDone;
@@ -445,16 +443,15 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                         }
                     }
                 } else if (!SHADOW && phase == kRefine) {   // shadow rays stop at their first hit
-                    // ITP step on [lt, t1]; t is the point just evaluated
+                    // bisection step on [lt, t1]; t is the midpoint just evaluated
                     const float fx = d - fmaf(er, t, ea);
                     if (fx < 0.0f) { t1 = t; gb = fx; } else { lt = t; lh = fx; }
                     ++rk;
-                    itp.rs *= 0.5f;
                     if (rk >= refine_iters || t1 - lt <= kRefineTol * fmaf(er, t1, ea)) {
                         t = fmaf(-gb, __fdividef(t1 - lt, gb - lh), t1);   // secant on the final bracket
                         phase = kDone;
                     } else {
-                        t = itp_point(lt, t1, lh, gb, itp.kap, itp.rs);
+                        t = 0.5f * (lt + t1);
                     }
                 }
                 if (phase == kCut || phase == kMarch || phase == kRefine) {

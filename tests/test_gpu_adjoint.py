@@ -186,6 +186,8 @@ def test_adjoint_matches_fp64_finite_differences(frt, orc, case):
     print("%s: %d stable pixels; rel err vs FP64 FD %s" % (case, keep.sum(),
                                                           {k: "%.2e" % v for k, v in report.items()}))
     expected = {name for name, grp in GROUPS.items() if set(grp) & set(slots)}
+    if case == "julia_cut":
+        expected.discard("c")   # the cut face covers the view; its surface pixels all border it
     assert set(report) == expected, (set(report), expected)
     for name, rel in report.items():
         assert rel < 1e-4, (name, rel, report)
@@ -338,7 +340,9 @@ def test_diff_set_adjoint_at_full_size_vs_fp64_fd(frt, orc):
             if not grp:
                 continue
             r = np.linalg.norm(refs[k][grp])
-            assert r > 0.0, (k, name)
+            if r == 0.0:   # no stable sampled pixel depends on this group (a plane that cuts nothing there)
+                assert np.all(gpu[k, grp] == 0.0), (k, name, gpu[k, grp])
+                continue
             rel[name] = np.linalg.norm(gpu[k, grp] - refs[k][grp]) / r
             worst = max(worst, rel[name])
         print("job %2d (%s): %d stable sampled pixels (mask %.2f); rel err %s"
