@@ -125,14 +125,21 @@ typedef struct {
  * threshold eps(t*)) hits, else 1; V is traced only when shadow != 0 and
  * N.L > 0.
  * FRT_SHADING_PHONG, the closest-hit shading of the paper's shaders, is
- * served by frt_render_scene only (the other renderers return
- * FRT_EUNSUPPORTED): the colour above plus a white highlight
+ * served by frt_render_scene, frt_render and frt_render_batch (the latter
+ * two trace such a job as a one-object scene with the identity placement;
+ * the adjoint and frt_render_batch_noalloc return FRT_EUNSUPPORTED): the
+ * colour above plus a white highlight
  * k_specular max(0, R.V)^shininess V (R = 2 (N.L) N - L, V = -dir, zero when
  * N.L <= 0), plus k_reflect F c_r, where c_r is the colour of the first hit
  * of the reflection ray (from p* + 4 eps(t*) N along dir - 2 (dir.N) N,
  * threshold eps(t*) + eps_rel s at distance s, against every object; its
  * own Lambert and highlight terms, no shadow ray; 0 on a miss) and
- * F = albedo + (1 - albedo)(1 - max(0, -dir.N))^5 (Schlick, per channel).  */
+ * F = albedo + (1 - albedo)(1 - max(0, -dir.N))^5 (Schlick, per channel).
+ * With this model the albedo of a hit (and of the reflection ray's hit) is
+ * coloured by the orbit trap T of its point (the colour parameters of the
+ * Mandelbulb distance listing: the minima of |x|, |y|, |z| and |w|^2 over
+ * the orbit): albedo_c + sum_k trap_colour[k][c] T_k, clamped to [0, 1]
+ * per channel; a zero trap_colour leaves the albedo as given.               */
 typedef struct {
     int32_t max_steps;          /* [1, 65536]                                */
     float eps_abs, eps_rel;     /* >= 0, not both 0                          */
@@ -149,6 +156,8 @@ typedef struct {
     float shininess;            /* [1, 10000] (Phong exponent)               */
     float k_reflect;            /* [0, 1] (reflection weight); these three   */
                                 /* are read only with FRT_SHADING_PHONG      */
+    float trap_colour[4][3];    /* finite; albedo change per unit of each    */
+                                /* trap component (read with _PHONG only)    */
 } frt_march;
 
 /* Output planes (device pointers, see the layout above).  depth, normal,
@@ -173,8 +182,8 @@ typedef struct {
 
 /* Device workspace needed by a call over n_jobs renders (work-queue
  * counters, the job table and the adjoint's table of upstream-gradient
- * pointers).  Any device allocation of at least this many bytes, 256-byte
- * aligned, serves.                                                          */
+ * pointers, or the object table of jobs traced as one-object scenes).  Any
+ * device allocation of at least this many bytes, 256-byte aligned, serves. */
 size_t frt_workspace_bytes(int32_t n_jobs);
 
 /* Render one view (the per-pixel path of Listings 2-5 and 7).

@@ -492,10 +492,20 @@ def render_scene(scene, pixels=None, samples=0):
             shadowed[idx[hit_k]] = True
         vis[lit[shadowed]] = 0.0
         status[lit[shadowed]] |= FLAG_SHADOWED
+    # orbit trap (R24) at the hit point, in the object's frame
+    trap = np.zeros((4, n))
+    for k, ob in enumerate(scene["objects"]):
+        m = np.nonzero(best == k)[0]
+        if m.size:
+            R, T, s = object_frame(ob)
+            trap[:, m] = orbit_trap(ob["fractal"], (o[m] + depth[m, None] * d[m] - T) @ R / s).T
+    phong = mc.get("shading", "lambert") == "phong"
     albedo = np.array(mc["albedo"], dtype=np.float64)
+    pal = np.array(mc.get("trap_colour", [[0.0] * 3] * 4), dtype=np.float64) if phong else np.zeros((4, 3))
+    alb = trap_albedo(albedo, pal, trap)                           # [3, n]
     lam = mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0.0, ndl) * vis
-    colour = albedo[:, None] * lam[None, :]
-    if mc.get("shading", "lambert") == "phong":
+    colour = alb * lam[None, :]
+    if phong:
         # R23: white Phong highlight (shadowed with the diffuse term), then one
         # reflection bounce weighted by Schlick's Fresnel term with f0 = albedo
         colour = colour + float(mc["k_specular"]) * _phong_spec(nrm, Ld, -d, ndl, float(mc["shininess"]))[None, :] * vis
@@ -506,37 +516,42 @@ def render_scene(scene, pixels=None, samples=0):
         q = o[h] + depth[h, None] * d[h] + 4.0 * eps_s[:, None] * nrm[h]
         rt = np.full(h.size, np.inf)
         rn = np.zeros((h.size, 3))
+        rtrap = np.zeros((4, h.size))
         for ob in scene["objects"]:
             R, T, s = object_frame(ob)
-            r = trace_rays(ob["fractal"], ob.get("planes", []), object_march(mc, s), (q - T) @ R / s, rd @ R,
-                           eps0=eps_s / s)
+            qo, rdo = (q - T) @ R / s, rd @ R
+            r = trace_rays(ob["fractal"], ob.get("planes", []), object_march(mc, s), qo, rdo, eps0=eps_s / s)
             tw = r["depth"] * s
             better = ((r["status"] & 7) >= STATUS_HIT) & (tw < rt)
             rt[better] = tw[better]
             rn[better] = r["normal"][better] @ R.T
+            if better.any():
+                bi = np.nonzero(better)[0]
+                rtrap[:, bi] = orbit_trap(ob["fractal"], qo[bi] + r["depth"][bi, None] * rdo[bi]).T
         rhit = np.isfinite(rt)
         rl = np.linalg.norm(rn, axis=1, keepdims=True)
         rn = np.where(rl > 0, rn / np.where(rl > 0, rl, 1.0), rn)
         rndl = rn @ Ld
-        c_r = albedo[:, None] * (mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0.0, rndl))[None, :]
+        ralb = trap_albedo(albedo, pal, rtrap)
+        c_r = ralb * (mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0.0, rndl))[None, :]
         c_r = c_r + float(mc["k_specular"]) * _phong_spec(rn, Ld, -rd, rndl, float(mc["shininess"]))[None, :]
         c_r = np.where(rhit[None, :], c_r, 0.0)
         cos_i = np.maximum(0.0, -dn)
-        F = albedo[:, None] + (1.0 - albedo[:, None]) * ((1.0 - cos_i) ** 5)[None, :]
+        ah = alb[:, h]
+        F = ah + (1.0 - ah) * ((1.0 - cos_i) ** 5)[None, :]
         colour[:, h] += float(mc["k_reflect"]) * F * c_r
         status[h[rhit]] |= FLAG_REFLECT_HIT
     colour = np.where(hit[None, :], colour, 0.0)
-    # orbit trap (R24) at the hit point, in the object's frame
-    trap = np.zeros((4, n))
-    for k, ob in enumerate(scene["objects"]):
-        m = np.nonzero(best == k)[0]
-        if m.size:
-            R, T, s = object_frame(ob)
-            trap[:, m] = orbit_trap(ob["fractal"], (o[m] + depth[m, None] * d[m] - T) @ R / s).T
     out = {"depth": depth, "normal": np.where(hit[None, :], nrm.T, 0.0), "colour": colour, "status": status,
            "object_id": best, "trap": trap}
     out.update(keep)
     return out
+
+
+def trap_albedo(albedo, palette, trap):
+    """Albedo of hits [3, n] coloured by their orbit traps [4, n] (R25): per
+    channel albedo_c + sum_k palette[k][c] T_k, clamped to [0, 1]."""
+    return np.clip(np.asarray(albedo, np.float64)[:, None] + np.asarray(palette, np.float64).T @ trap, 0.0, 1.0)
 
 
 def _phong_spec(nrm, L, V, ndl, shininess):

@@ -54,7 +54,8 @@ class March(ctypes.Structure):
                 ("step_clamp", ctypes.c_float), ("t_max", ctypes.c_float), ("normal_mode", ctypes.c_int32),
                 ("refine_iters", ctypes.c_int32), ("shadow", ctypes.c_int32), ("light_dir", f3), ("albedo", f3),
                 ("k_ambient", ctypes.c_float), ("k_diffuse", ctypes.c_float), ("shading", ctypes.c_int32),
-                ("k_specular", ctypes.c_float), ("shininess", ctypes.c_float), ("k_reflect", ctypes.c_float)]
+                ("k_specular", ctypes.c_float), ("shininess", ctypes.c_float), ("k_reflect", ctypes.c_float),
+                ("trap_colour", ctypes.c_float * 12)]
 
 
 class Frame(ctypes.Structure):
@@ -177,7 +178,8 @@ def make_march(m):
                  float(m["t_max"]), mode, int(m.get("refine_iters", 12)), int(bool(m["shadow"])),
                  f3(*m["light_dir"]), f3(*m["albedo"]), float(m["k_ambient"]), float(m["k_diffuse"]),
                  SHADING_MODELS[m.get("shading", "lambert")], float(m.get("k_specular", 0.0)),
-                 float(m.get("shininess", 1.0)), float(m.get("k_reflect", 0.0)))
+                 float(m.get("shininess", 1.0)), float(m.get("k_reflect", 0.0)),
+                 (ctypes.c_float * 12)(*[float(x) for row in m.get("trap_colour", [[0.0] * 3] * 4) for x in row]))
 
 
 def _ptr(t):

@@ -219,6 +219,7 @@ bool validate(const frt_camera* cam, const frt_fractal* fr, const frt_plane* pla
         }
         if (!(mc->shininess >= 1.0f && mc->shininess <= 1e4f)) { why = "shininess must be in [1, 10000]"; return false; }
         if (!(mc->k_reflect >= 0.0f && mc->k_reflect <= 1.0f)) { why = "k_reflect must be in [0, 1]"; return false; }
+        if (!finite_n(&mc->trap_colour[0][0], 12)) { why = "non-finite trap_colour"; return false; }
     }
     if (need_outputs) {
         if (!out || !out->depth || !out->normal || !out->colour || !out->status) {
@@ -346,6 +347,14 @@ void pack(const frt_camera* cam, const frt_fractal* fr, const frt_plane* planes,
     J.k_s = mc->k_specular;
     J.shininess = mc->shininess;
     J.k_r = mc->k_reflect;
+    J.trap_colour = 0;
+    if (mc->shading == FRT_SHADING_PHONG) {
+        for (int k = 0; k < 4; ++k)
+            for (int c = 0; c < 3; ++c) {
+                J.trap_pal[k][c] = mc->trap_colour[k][c];
+                if (mc->trap_colour[k][c] != 0.0f) J.trap_colour = 1;
+            }
+    }
     // outputs
     J.depth = out.depth;
     J.normal = out.normal;
@@ -464,25 +473,27 @@ void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
 
 frt_status record_error(frt_status s, const char* msg) { return fail(s, msg ? msg : ""); }
 
-frt_status batch_validate(const frt_job* jobs, int32_t n_jobs) {
+frt_status batch_validate(const frt_job* jobs, int32_t n_jobs, bool allow_closest_hit) {
     for (int i = 0; i < n_jobs; ++i) {
         std::string why;
         const frt_job& jb = jobs[i];
         if (!validate(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, &jb.out, true, why))
             return fail(FRT_EINVAL, "job " + std::to_string(i) + ": " + why);
-        if (jb.march.shading != FRT_SHADING_LAMBERT)
-            return fail(FRT_EUNSUPPORTED,
-                        "job " + std::to_string(i) + ": the closest-hit shading model is rendered by frt_render_scene");
+        if (jb.march.shading != FRT_SHADING_LAMBERT && !allow_closest_hit)
+            return fail(FRT_EUNSUPPORTED, "job " + std::to_string(i) +
+                                              ": the closest-hit shading model is not served by this entry point");
     }
     return FRT_OK;
 }
 
 frt_status batch_layout(const frt_job* jobs, int32_t n_jobs, WorkspaceHeader& hdr, TraceGroup* groups, int& n_groups,
-                        bool (*sink)(void* ctx, const JobDev& J), void* ctx) {
+                        bool (*sink)(void* ctx, const JobDev& J), void* ctx, bool closest_hit_elsewhere) {
     n_groups = 0;
-    // every job is validated before anything is packed or launched
-    frt_status vs = batch_validate(jobs, n_jobs);
+    // every job is validated before anything is packed or launched; jobs
+    // with the closest-hit shading model are left to the caller
+    frt_status vs = batch_validate(jobs, n_jobs, closest_hit_elsewhere);
     if (vs != FRT_OK) return vs;
+    int n_table = 0;
     // lay the rays out variant by variant: group v is one contiguous range of
     // the ray index space traced by its own kernels (the table order is
     // internal; outputs travel with each job)
@@ -493,7 +504,8 @@ frt_status batch_layout(const frt_job* jobs, int32_t n_jobs, WorkspaceHeader& hd
         bool shadow = false;
         for (int i = 0; i < n_jobs; ++i) {
             const frt_job& jb = jobs[i];
-            if (variant_of_frac(&jb.frac) != v) continue;
+            if (variant_of_frac(&jb.frac) != v || jb.march.shading != FRT_SHADING_LAMBERT) continue;
+            ++n_table;
             JobDev J;
             pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, begin, J);
             begin += J.ray_count;
@@ -510,8 +522,21 @@ frt_status batch_layout(const frt_job* jobs, int32_t n_jobs, WorkspaceHeader& hd
         if (!make_cfg(trace_kernel_symbol(v, true), v, begin - g0, g.cfg, why)) return fail(FRT_EHIP, why);
     }
     hdr.total_rays = static_cast<unsigned long long>(begin);
-    hdr.n_jobs = n_jobs;
+    hdr.n_jobs = n_table;
     return FRT_OK;
+}
+
+// A job with the closest-hit shading model as a one-object scene: the
+// object placed by the identity, the job's camera, march and outputs.
+void pack_scene_job(const frt_job& jb, SceneObject& S, JobDev& camJ) {
+    std::memset(&S, 0, sizeof(S));
+    frt_frame none{};
+    pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, none, 0, S.job);
+    S.rot[0] = S.rot[4] = S.rot[8] = 1.0f;
+    S.scale = 1.0f;
+    S.inv_scale = 1.0f;
+    S.variant = variant_of(S.job);
+    pack(&jb.cam, &jb.frac, jb.planes, jb.n_planes, &jb.march, jb.out, 0, camJ);
 }
 
 }  // namespace frt
@@ -521,7 +546,7 @@ extern "C" {
 
 size_t frt_workspace_bytes(int32_t n_jobs) {
     if (n_jobs < 1) n_jobs = 1;
-    const int64_t per_job = int64_t(sizeof(JobDev)) + int64_t(sizeof(frt::AdjointJob));
+    const int64_t per_job = int64_t(frt::kWorkspaceBytesPerJob);
     return size_t(round_up(int64_t(sizeof(WorkspaceHeader)) + int64_t(n_jobs) * per_job, 256));
 }
 
@@ -601,10 +626,33 @@ frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_
     g_last_error.clear();
     std::string why;
     if (!validate(cam, frac, planes, n_planes, march, &out, true, why)) return fail(FRT_EINVAL, why);
-    if (march->shading != FRT_SHADING_LAMBERT)
-        return fail(FRT_EUNSUPPORTED, "the closest-hit shading model is rendered by frt_render_scene");
     frt_status s = check_workspace(workspace, ws_bytes, 1);
     if (s != FRT_OK) return s;
+    if (march->shading != FRT_SHADING_LAMBERT) {
+        // the closest-hit model: a one-object scene with the identity placement
+        frt_job jb;
+        std::memset(&jb, 0, sizeof(jb));
+        jb.cam = *cam;
+        jb.frac = *frac;
+        for (int k = 0; k < n_planes; ++k) jb.planes[k] = planes[k];
+        jb.n_planes = n_planes;
+        jb.march = *march;
+        jb.out = out;
+        frt::SceneObject S;
+        JobDev camJ;
+        frt::pack_scene_job(jb, S, camJ);
+        WorkspaceHeader hdr;
+        std::memset(&hdr, 0, sizeof(hdr));
+        const void* parts[2] = {&hdr, &S};
+        const size_t sizes[2] = {sizeof(hdr), sizeof(S)};
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        s = upload_parts(parts, sizes, 2, workspace, st);
+        if (s != FRT_OK) return s;
+        const auto* objs = reinterpret_cast<const frt::SceneObject*>(static_cast<char*>(workspace) + sizeof(hdr));
+        hipError_t e = frt::launch_scene(objs, 1, camJ, nullptr, nullptr, st);
+        if (e != hipSuccess) return hip_fail(e, "scene launch");
+        return FRT_OK;
+    }
     JobDev J;
     pack(cam, frac, planes, n_planes, march, out, 0, J);
     frt::TraceGroup g;
@@ -634,18 +682,41 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
         static_cast<std::vector<JobDev>*>(ctx)->push_back(J);
         return true;
     };
-    s = frt::batch_layout(jobs, n_jobs, hdr, group_arr, ng, push, &table);
+    // Lambert jobs go to the persistent trace; jobs with the closest-hit
+    // model are traced as one-object scenes, their objects after the table
+    s = frt::batch_layout(jobs, n_jobs, hdr, group_arr, ng, push, &table, true);
     if (s != FRT_OK) return s;
+    std::vector<frt::SceneObject> sobj;
+    std::vector<JobDev> scam;
+    for (int i = 0; i < n_jobs; ++i) {
+        if (jobs[i].march.shading == FRT_SHADING_LAMBERT) continue;
+        sobj.emplace_back();
+        scam.emplace_back();
+        frt::pack_scene_job(jobs[i], sobj.back(), scam.back());
+    }
     std::vector<frt::TraceGroup> groups(group_arr, group_arr + ng);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    s = upload_table(table, hdr, workspace, st);
+    const void* parts[3] = {&hdr, table.data(), sobj.data()};
+    const size_t sizes[3] = {sizeof(hdr), table.size() * sizeof(JobDev), sobj.size() * sizeof(frt::SceneObject)};
+    s = upload_parts(parts, sizes, 3, workspace, st);
     if (s != FRT_OK) return s;
-    const JobDev* dev_jobs = reinterpret_cast<const JobDev*>(static_cast<char*>(workspace) + sizeof(WorkspaceHeader));
+    char* base = static_cast<char*>(workspace);
+    const JobDev* dev_jobs = reinterpret_cast<const JobDev*>(base + sizeof(WorkspaceHeader));
+    const auto* dev_objs =
+        reinterpret_cast<const frt::SceneObject*>(base + sizeof(WorkspaceHeader) + table.size() * sizeof(JobDev));
     WorkspaceHeader* dhdr = static_cast<WorkspaceHeader*>(workspace);
+    auto scenes = [&]() -> frt_status {
+        for (size_t k = 0; k < sobj.size(); ++k) {
+            hipError_t e = frt::launch_scene(dev_objs + k, 1, scam[k], nullptr, nullptr, st);
+            if (e != hipSuccess) return hip_fail(e, "scene launch");
+        }
+        return FRT_OK;
+    };
+    if (ng == 0) return scenes();
     if (!use_graph) {
         hipError_t e = frt::launch_trace(groups.data(), ng, true, dev_jobs, table[0], dhdr, st, timing_marks());
         if (e != hipSuccess) return hip_fail(e, "trace launch");
-        return FRT_OK;
+        return scenes();
     }
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -680,7 +751,7 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
     }
     e = hipGraphLaunch(exec, st);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-    return FRT_OK;
+    return scenes();
 }
 
 size_t frt_noalloc_scratch_bytes(void) { return frt::noalloc_scratch_bytes(); }
@@ -690,7 +761,7 @@ frt_status frt_render_batch_noalloc(const frt_job* jobs, int32_t n_jobs, void* s
     if (!jobs || n_jobs < 1) return fail(FRT_EINVAL, "jobs is null or n_jobs < 1");
     if (n_jobs > FRT_NOALLOC_MAX_JOBS) return fail(FRT_EINVAL, "n_jobs exceeds FRT_NOALLOC_MAX_JOBS");
     // every job is checked before the first device call
-    frt_status vs = frt::batch_validate(jobs, n_jobs);
+    frt_status vs = frt::batch_validate(jobs, n_jobs, false);
     if (vs != FRT_OK) return vs;
     hipError_t he = hipSuccess;
     char* ws = static_cast<char*>(frt::noalloc_scratch(he));
@@ -734,7 +805,7 @@ frt_status frt_render_batch_noalloc(const frt_job* jobs, int32_t n_jobs, void* s
     WorkspaceHeader hdr;
     frt::TraceGroup groups[frt::kNumVariants];
     int ng = 0;
-    frt_status s = frt::batch_layout(jobs, n_jobs, hdr, groups, ng, put, &sk);
+    frt_status s = frt::batch_layout(jobs, n_jobs, hdr, groups, ng, put, &sk, false);
     if (s != FRT_OK) return s;
     if (!sk.flush()) return hip_fail(sk.err, "job table upload");
     // the header's fields (its first KiB; the claim counters after them are

@@ -43,10 +43,16 @@ const void* trace_kernel_symbol(int variant, bool batch);
 // header's ranges, ray total and job count (the claim counters stay zero)
 // and one launch group per variant present (groups holds kNumVariants).
 // Errors are recorded for frt_last_error().
+// With closest_hit_elsewhere, jobs with the closest-hit shading model pass
+// validation and are left out of the table (hdr.n_jobs counts the table);
+// otherwise they are refused with FRT_EUNSUPPORTED.
 frt_status batch_layout(const frt_job* jobs, int32_t n_jobs, WorkspaceHeader& hdr, TraceGroup* groups, int& n_groups,
-                        bool (*sink)(void* ctx, const JobDev& J), void* ctx);
+                        bool (*sink)(void* ctx, const JobDev& J), void* ctx, bool closest_hit_elsewhere);
 // The validation pass of batch_layout alone (host only, no device call).
-frt_status batch_validate(const frt_job* jobs, int32_t n_jobs);
+frt_status batch_validate(const frt_job* jobs, int32_t n_jobs, bool allow_closest_hit);
+// A job with the closest-hit shading model as a one-object scene (identity
+// placement) and the scene kernel's camera / output descriptor.
+void pack_scene_job(const frt_job& jb, SceneObject& S, JobDev& camJ);
 // frt_last_error() bookkeeping for entry points outside frt_api.cpp.
 void set_last_error(const char* msg);
 frt_status record_error(frt_status s, const char* msg);

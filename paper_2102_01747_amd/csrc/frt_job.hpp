@@ -61,6 +61,8 @@ struct alignas(16) JobDev {
     float k_a, k_d;
     int32_t shading;
     float k_s, shininess, k_r;
+    float trap_pal[4][3];    // closest-hit shading: albedo change per unit trap component
+    int32_t trap_colour;     // trap_pal has a non-zero entry
     // outputs (SoA planes of npix)
     float* depth;
     float* normal;
@@ -132,5 +134,11 @@ struct alignas(256) WorkspaceHeader {
 };
 static_assert(sizeof(WorkspaceHeader) == 1024 + kNumVariants * 2 * kQueueSlots * 256,
               "workspace header: 1 KiB of fields, then the claim counters");
+
+// Workspace bytes per job after the header: a job-table entry and the
+// adjoint's entry, or an object-table entry for a job traced as a scene.
+constexpr unsigned kWorkspaceBytesPerJob =
+    sizeof(JobDev) + sizeof(AdjointJob) > sizeof(SceneObject) ? sizeof(JobDev) + sizeof(AdjointJob)
+                                                               : sizeof(SceneObject);
 
 }  // namespace frt

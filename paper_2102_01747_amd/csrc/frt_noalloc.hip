@@ -19,7 +19,7 @@ namespace {
 
 // header + FRT_NOALLOC_MAX_JOBS jobs, laid out as frt_workspace_bytes() does
 constexpr size_t kScratchBytes =
-    (sizeof(WorkspaceHeader) + size_t(FRT_NOALLOC_MAX_JOBS) * (sizeof(JobDev) + sizeof(AdjointJob)) + 255) / 256 * 256;
+    (sizeof(WorkspaceHeader) + size_t(FRT_NOALLOC_MAX_JOBS) * kWorkspaceBytesPerJob + 255) / 256 * 256;
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 

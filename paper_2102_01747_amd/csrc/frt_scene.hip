@@ -20,7 +20,9 @@
 // white Phong highlight is added, and one reflection ray, traced against
 // every object with the threshold carried on from eps(t*), adds its hit's
 // Lambert and highlight terms weighted by Schlick's Fresnel term
-// (f0 = albedo).  The orbit trap at the hit point is written on request.
+// (f0 = albedo); there a trap palette colours each hit's albedo by the
+// orbit trap of its point.  The orbit trap at the hit point is written on
+// request.
 #include <hip/hip_runtime.h>
 
 #include "frt_internal.hpp"
@@ -168,6 +170,16 @@ __device__ __forceinline__ float phong_spec(float nx, float ny, float nz, const 
     return rv > 0.0f ? hw_exp2(shininess * hw_log2(rv)) : 0.0f;
 }
 
+// Trap colouring of the closest-hit model: albedo_c + sum_k pal[k][c] T_k,
+// clamped to [0, 1].
+__device__ __forceinline__ void trap_albedo(const JobDev& cam, const float (&tr)[4], float (&alb)[3]) {
+    for (int c = 0; c < 3; ++c) {
+        float a = cam.albedo[c];
+        for (int k = 0; k < 4; ++k) a = fmaf(cam.trap_pal[k][c], tr[k], a);
+        alb[c] = fminf(fmaxf(a, 0.0f), 1.0f);
+    }
+}
+
 // world point / direction -> object frame (x_obj = R^T (x - T) / s; directions R^T d)
 __device__ __forceinline__ void to_object(const SceneObject& S, float x, float y, float z, bool point, float& ox,
                                           float& oy, float& oz) {
@@ -312,8 +324,18 @@ __global__ void __launch_bounds__(256) scene_kernel(const SceneObject* __restric
             }
         }
     }
+    // albedo of the hit: the given one, or with the closest-hit model and a
+    // trap palette, coloured by the orbit trap of the hit point
+    float alb[3] = {cam.albedo[0], cam.albedo[1], cam.albedo[2]};
+    float tr[4] = {0.f, 0.f, 0.f, 0.f};
+    const bool need_trap = trap != nullptr || (cam.shading == 1 && cam.trap_colour);
+    if (need_trap) {
+        const OrbitParams P = orbit_params(J);
+        trap_any(S.variant, P, fmaf(hit.t, bdx, box), fmaf(hit.t, bdy, boy), fmaf(hit.t, bdz, boz), tr);
+        if (cam.shading == 1 && cam.trap_colour) trap_albedo(cam, tr, alb);
+    }
     const float lam = fmaf(cam.k_d * vis, fmaxf(ndl, 0.0f), cam.k_a);
-    float col[3] = {cam.albedo[0] * lam, cam.albedo[1] * lam, cam.albedo[2] * lam};
+    float col[3] = {alb[0] * lam, alb[1] * lam, alb[2] * lam};
     if (cam.shading == 1) {
         // closest-hit shading: highlight, then one reflection bounce
         const float spec = cam.k_s * vis * phong_spec(nx, ny, nz, cam.light, -dx, -dy, -dz, ndl, cam.shininess);
@@ -385,6 +407,13 @@ __global__ void __launch_bounds__(256) scene_kernel(const SceneObject* __restric
                 wy = uy;
                 wz = uz;
             }
+            float ralb[3] = {cam.albedo[0], cam.albedo[1], cam.albedo[2]};
+            if (cam.trap_colour) {
+                const OrbitParams P = orbit_params(JO);
+                float rtr[4];
+                trap_any(O.variant, P, fmaf(rh.t, rvx, rox), fmaf(rh.t, rvy, roy), fmaf(rh.t, rvz, roz), rtr);
+                trap_albedo(cam, rtr, ralb);
+            }
             const float rndl = fmaf(wx, cam.light[0], fmaf(wy, cam.light[1], wz * cam.light[2]));
             const float rlam = fmaf(cam.k_d, fmaxf(rndl, 0.0f), cam.k_a);
             const float rspec = cam.k_s * phong_spec(wx, wy, wz, cam.light, -rdx, -rdy, -rdz, rndl, cam.shininess);
@@ -392,17 +421,13 @@ __global__ void __launch_bounds__(256) scene_kernel(const SceneObject* __restric
             const float ci2 = ci * ci;
             const float f5 = ci2 * ci2 * ci;
             for (int c = 0; c < 3; ++c) {
-                const float F = fmaf(1.0f - cam.albedo[c], f5, cam.albedo[c]);
-                col[c] = fmaf(cam.k_r * F, fmaf(cam.albedo[c], rlam, rspec), col[c]);
+                const float F = fmaf(1.0f - alb[c], f5, alb[c]);
+                col[c] = fmaf(cam.k_r * F, fmaf(ralb[c], rlam, rspec), col[c]);
             }
         }
     }
-    if (trap) {
-        const OrbitParams P = orbit_params(J);
-        float tr[4];
-        trap_any(S.variant, P, fmaf(hit.t, bdx, box), fmaf(hit.t, bdy, boy), fmaf(hit.t, bdz, boz), tr);
+    if (trap)
         for (int c = 0; c < 4; ++c) trap[c * NP + p] = tr[c];
-    }
     cam.depth[p] = tw;
     cam.normal[p] = nx;
     cam.normal[NP + p] = ny;

@@ -161,6 +161,30 @@ def normal_ill_conditioned(orc, fr, mc, pts, dirs, eps, tol=2e-4, margin=1e-4):
     return (sens > tol) | low
 
 
+def trap_ill_conditioned(orc, fr, pts, seeds=4, tol=1e-4, margin=1e-4):
+    """Per point: is the FP64 orbit trap ill-conditioned at float32
+    resolution?  When a trap component moves by more than tol under the
+    rounding probe of every body's power (relative 2 p 2^-24, `seeds`
+    draws) or under a shift of the point by 2^-23 max|p_k| along each axis,
+    or an orbit body comes within `margin` (relative) of the bailout."""
+    pts = np.asarray(pts, np.float64)
+    if len(pts) == 0:
+        return np.zeros(0, bool)
+    ref = orc.orbit_trap(fr, pts)
+    rel = 2.0 * fr["power"] * 2.0 ** -24
+    ill = np.zeros(len(pts), bool)
+    for sd in range(seeds):
+        ill |= np.any(np.abs(orc.orbit_trap_perturbed(fr, pts, rel, 2000 + sd) - ref) > tol, axis=1)
+    delta = 2.0 ** -23 * np.abs(pts).max(1)
+    for ax in range(3):
+        for sg in (-1.0, 1.0):
+            q = pts.copy()
+            q[:, ax] += sg * delta
+            ill |= np.any(np.abs(orc.orbit_trap(fr, q) - ref) > tol, axis=1)
+    mg, _ = orc.escape_margin(fr, pts)
+    return ill | (mg < margin)
+
+
 def ray_interval(orc, job, orig, dirs):
     """The oracle's search interval [lo, hi] of each ray: [eps_abs, t_max]
     cut by the bounding sphere and the kept half-spaces (empty: lo > hi)."""
@@ -219,8 +243,13 @@ def adjoint_mask(orc, job, g, o, pixels=None, neigh_diff=None):
     sides report the same smooth hit class (refined surface hit or cut
     face) at the same root (depths within 2 eps), the pixel is outside B,
     a surface hit's normal is well conditioned at float32 resolution and
-    every normal tap's orbit escapes.  Elsewhere the two sides may
-    legitimately differentiate different branches."""
+    every normal tap's orbit escapes, and the oracle's final march bracket
+    holds a single crossing of d - eps.  Elsewhere the two sides may
+    legitimately differentiate different branches: a bracket with several
+    crossings holds roots closer together than 2 eps (typically two smooth
+    roots on either side of a jump of the estimate, where the escape count
+    changes), so the depth test cannot tell which one each side polished,
+    and the derivatives at the two differ by far more than the 1e-3 bar."""
     cam, mc, fr = job["camera"], job["march"], job["fractal"]
     H, W = cam["height"], cam["width"]
     if pixels is None:
@@ -248,6 +277,8 @@ def adjoint_mask(orc, job, g, o, pixels=None, neigh_diff=None):
         tp = orc.tap_points(pts, eps, mc["normal_mode"])
         _, esc = orc.escape_margin(fr, tp.reshape(-1, 3))
         bad |= ~esc.reshape(surf.size, tp.shape[1]).all(1)
+        _, _, crossings = orc.bracket_crossings(job, pixels[surf])
+        bad |= crossings > 1
         M[surf[bad]] = False
     return M
 
@@ -559,6 +590,20 @@ def compare_scene(orc, sc, g, o, neigh_diff):
     ang = angle(gn, n_at) if idx.size else np.zeros(0)
     _normal_stats(stats, ang, sens, ill)
     wc = ~ill
+    # with trap colouring the albedo follows the orbit trap of the hit point:
+    # colour is compared where that trap is well conditioned too
+    pal = np.asarray(mc.get("trap_colour", [[0.0] * 3] * 4), np.float64)
+    if mc.get("shading", "lambert") == "phong" and np.any(pal != 0.0):
+        tri = np.zeros(idx.size, bool)
+        for k, ob in enumerate(sc["objects"]):
+            sel = np.nonzero(gid[idx] == k)[0]
+            if sel.size == 0:
+                continue
+            R, T, s = orc.object_frame(ob)
+            pi = idx[sel]
+            tri[sel] = trap_ill_conditioned(orc, ob["fractal"], (orig[pi] + gd[sel, None] * dirs[pi] - T) @ R / s)
+        stats["trap_boundary_frac"] = float(tri.mean()) if idx.size else 0.0
+        wc = wc & ~tri
     keep = np.zeros(n, bool)
     keep[idx[wc]] = True
     # colour where the shadow outcome and (closest-hit shading) the
@@ -578,12 +623,13 @@ def compare_scene(orc, sc, g, o, neigh_diff):
 
 def assert_scene_parity(stats, id_agree=0.999, normal_ok=0.999, colour_ok=None, reflect_agree=0.995,
                         max_boundary=0.10, max_normal_boundary=0.05, max_depth_other=0.002,
-                        normal_conditioned=0.995):
+                        normal_conditioned=0.995, max_trap_boundary=0.2):
     msg = str(stats)
     assert stats["boundary_frac"] <= max_boundary, msg
     assert stats["normal_boundary_frac"] <= max_normal_boundary, msg
     assert stats["depth_other_root"] <= max(1, max_depth_other * stats["compared"]), msg
     assert stats["normal_ok_conditioned"] >= normal_conditioned, msg
+    assert stats.get("trap_boundary_frac", 0.0) <= max_trap_boundary, msg
     assert stats["reflect_agree"] >= reflect_agree, msg
     assert stats["id_agree"] >= id_agree, msg
     assert stats["hit_agree"] >= id_agree, msg

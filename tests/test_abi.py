@@ -142,7 +142,9 @@ def test_render_validation_on_the_host():
     case(setitem(("march", "normal_mode"), 5), frt.FRT_EINVAL, "unknown normal_mode")
     case(setitem(("march", "refine_iters"), 33), frt.FRT_EINVAL, "refine_iters")
     case(lambda j: None, frt.FRT_EINVAL, "null output plane", frame=frt.Frame(fake, None, fake, fake, None))
-    case(lambda j: j.update(march=W.phong(j["march"])), frt.FRT_EUNSUPPORTED, "frt_render_scene")
+    # the closest-hit model: its palette is validated like every parameter
+    bad_pal = [[0.0] * 3, [float("inf"), 0.0, 0.0], [0.0] * 3, [0.0] * 3]
+    case(lambda j: j.update(march=dict(W.phong(j["march"]), trap_colour=bad_pal)), frt.FRT_EINVAL, "trap_colour")
     # a valid job, then the workspace checks
     case(lambda j: None, frt.FRT_EINVAL, "workspace is null", workspace=None)
     case(lambda j: None, frt.FRT_EINVAL, "aligned", workspace=ctypes.c_void_p(0x100008))
@@ -180,7 +182,12 @@ def test_batch_and_backward_validation_on_the_host():
     assert b"job 2" in L.frt_last_error() and b"max_iter" in L.frt_last_error()
     assert L.frt_render_batch(table([good]), 1, ws, 1 << 20, 2, None) == frt.FRT_EINVAL   # use_graph
     assert L.frt_render_batch(table([good]), 1, ws, 64, 0, None) == frt.FRT_ENOMEM
-    # the entry point that allocates nothing checks the same before any device call
+    # the entry point that allocates nothing checks the same before any device
+    # call, and leaves the closest-hit model to the other renderers
+    phong1 = copy.deepcopy(good)
+    phong1["march"] = W.phong(phong1["march"])
+    assert L.frt_render_batch_noalloc(table([good, phong1]), 2, None) == frt.FRT_EUNSUPPORTED
+    assert b"job 1" in L.frt_last_error()
     assert L.frt_render_batch_noalloc(arr, 3, None) == frt.FRT_EINVAL
     assert b"job 2" in L.frt_last_error() and b"max_iter" in L.frt_last_error()
     assert L.frt_render_batch_noalloc(None, 1, None) == frt.FRT_EINVAL

@@ -296,7 +296,7 @@ def test_diff_set_adjoint_at_full_size_vs_fp64_fd(frt, orc):
     and ONE backward call over all 16 jobs (the job cursor, per-job flushes
     and atomics of the many-job path).  Loss: squared colour error to the
     target renders at offset parameters, over a seeded stratified sample of
-    pixels per job (one per 16 x 16 cell) that are stable under every FD
+    pixels per job (one per 12 x 12 cell) that are stable under every FD
     perturbation; per job and parameter group the adjoint must agree with
     FP64 central differences of the oracle to a relative 1e-3."""
     from parity import sampled_adjoint_mask
@@ -308,7 +308,7 @@ def test_diff_set_adjoint_at_full_size_vs_fp64_fd(frt, orc):
     gcs, refs, used = [], [], []
     for k, (job, fr, tf) in enumerate(zip(jobs, frames, tframes)):
         slots = [0, 1, 2, 3, 5, 6, 7, 8] if job["fractal"]["kind"] == "julia" else [4, 5, 6, 7, 8]
-        pix = W.stratified_pixels(512, 512, 16, seed=40 + k)
+        pix = W.stratified_pixels(512, 512, 12, seed=40 + k)
         M, g, o = sampled_adjoint_mask(orc, job, fr, pix)
         idx = pix[M]
         J, taps = orc.pixel_jacobian(job, idx)

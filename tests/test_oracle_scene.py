@@ -152,11 +152,58 @@ def _rho(eps):
 
 
 def _phong_closed(N, L, V, albedo, mc):
+    """Phong colour [3, n]; albedo [3] or per point [3, n]."""
     ndl = N @ L
     Rl = 2.0 * ndl[:, None] * N - L
     spec = np.where(ndl > 0, np.maximum(0.0, np.einsum("ij,ij->i", Rl, V)) ** mc["shininess"], 0.0)
-    return albedo[:, None] * (mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0, ndl))[None, :] + \
+    alb = albedo if albedo.ndim == 2 else albedo[:, None]
+    return alb * (mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0, ndl))[None, :] + \
         mc["k_specular"] * spec[None, :]
+
+
+def _trap_c0(p, max_iter, bailout2):
+    """Orbit trap of a c = 0 degree-2 Julia point in closed form: z_k =
+    zeta^(2^k) in span{1, v_hat} with zeta = x + i |v| (R24's minima of |x|,
+    |y|, |z| and |z|^2 over the start point and every body run)."""
+    v = p[1:]
+    vn = np.linalg.norm(v)
+    tr = [abs(p[0]), abs(p[1]), abs(p[2]), p @ p]
+    z = complex(p[0], vn)
+    for _ in range(max_iter):
+        z = z * z
+        comp = [abs(z.real), abs(z.imag * v[0] / vn), abs(z.imag * v[1] / vn), abs(z) ** 2]
+        tr = [min(a, b) for a, b in zip(tr, comp)]
+        if abs(z) ** 2 > bailout2:
+            break
+    return np.array(tr)
+
+
+def _trap_albedo(albedo, pal, traps):
+    return np.clip(albedo[:, None] + np.asarray(pal, np.float64).T @ traps, 0.0, 1.0)
+
+
+def test_trap_colouring_on_the_c0_ball_is_closed_form(orc):
+    """The closest-hit shading with the trap palette on one c = 0 ball: each
+    hit's albedo is albedo + palette . T, clamped, with the trap T of the
+    hit point in closed form (complex powers), and the colour is the Phong
+    term of the radial normal with that albedo."""
+    mc = W.phong(W.march(256, eps_abs=1e-3, normal_mode="analytic"), trap_colour=True)
+    sc = W.scene(W.camera((0.3, 0.8, 3.0), 80, 80), [_ball((0.0, 0.0, 0.0), 1.0)], mc)
+    out = orc.render_scene(sc)
+    hit = np.nonzero(out["object_id"] == 0)[0]
+    assert hit.size > 1000
+    o, d = orc.camera_rays(sc["camera"], hit)
+    p = o + out["depth"][hit, None] * d
+    fr = sc["objects"][0]["fractal"]
+    _, T0, s0 = orc.object_frame(sc["objects"][0])
+    traps = np.array([_trap_c0((q - T0) / s0, fr["max_iter"], fr["bailout2"]) for q in p]).T
+    alb = _trap_albedo(np.array(mc["albedo"], dtype=np.float64), mc["trap_colour"], traps)
+    assert np.ptp(alb, axis=1).min() > 0.05        # the palette does colour the ball
+    N = p / np.linalg.norm(p, axis=1, keepdims=True)
+    L = np.array(mc["light_dir"], dtype=np.float64)
+    L /= np.linalg.norm(L)
+    ref = _phong_closed(N, L, -d, alb, mc)
+    assert np.abs(out["colour"][:, hit] - ref).max() < 1e-6
 
 
 def test_phong_on_the_c0_ball_is_closed_form(orc):
@@ -177,12 +224,15 @@ def test_phong_on_the_c0_ball_is_closed_form(orc):
     assert np.abs(out["colour"][:, hit] - ref).max() < 1e-6
 
 
-def test_reflection_between_two_balls_is_closed_form(orc):
+@pytest.mark.parametrize("trap_colour", [False, True])
+def test_reflection_between_two_balls_is_closed_form(orc, trap_colour):
     """Two c = 0 balls (radius s rho_eps): where a reflection ray from ball A
     meets ball B (ray-sphere intersection in closed form), the colour is
     A's Phong term plus 0.1 Schlick(f0 = albedo) times B's Phong term at the
-    intersection; elsewhere the reflection adds nothing."""
-    mc = W.phong(W.march(256, eps_abs=1e-3, t_max=20.0, normal_mode="analytic"))
+    intersection; elsewhere the reflection adds nothing.  With the trap
+    palette, A's albedo (also Fresnel's f0) and B's albedo at the
+    reflected hit are coloured by the closed-form traps of the two points."""
+    mc = W.phong(W.march(256, eps_abs=1e-3, t_max=20.0, normal_mode="analytic"), trap_colour=trap_colour)
     A, B = (-0.7, 0.0, 0.0), (0.75, 0.1, -0.3)
     sA, sB = 0.6, 0.5
     sc = W.scene(W.camera((0.0, 0.3, 3.0), 128, 96), [_ball(A, sA), _ball(B, sB)], mc)
@@ -196,7 +246,15 @@ def test_reflection_between_two_balls_is_closed_form(orc):
     L = np.array(mc["light_dir"], dtype=np.float64)
     L /= np.linalg.norm(L)
     albedo = np.array(mc["albedo"], dtype=np.float64)
-    base = _phong_closed(N, L, -d, albedo, mc)
+    pal = mc.get("trap_colour", [[0.0] * 3] * 4)
+    fr = sc["objects"][0]["fractal"]
+    # traps in each object's own frame (its float32 placement: the trap is
+    # sensitive to the point at the 1e-7 level)
+    _, TA, sAf = orc.object_frame(sc["objects"][0])
+    _, TB, sBf = orc.object_frame(sc["objects"][1])
+    albA = _trap_albedo(albedo, pal, np.array([_trap_c0((q - TA) / sAf, fr["max_iter"], fr["bailout2"])
+                                                for q in p]).T)
+    base = _phong_closed(N, L, -d, albA, mc)
     # reflected ray against B's eps-level sphere (world radius sB rho(eps_B))
     eps_s = mc["eps_abs"] + 0.0 * t
     dn = np.einsum("ij,ij->i", d, N)
@@ -214,8 +272,26 @@ def test_reflection_between_two_balls_is_closed_form(orc):
     assert np.sum(meets & clear) > 30
     hp = q + np.where(meets, th, 0.0)[:, None] * rd
     NB = (hp - Bv) / np.linalg.norm(hp - Bv, axis=1, keepdims=True)
-    c_r = _phong_closed(np.where(meets[:, None], NB, 0.0), L, -rd, albedo, mc)
-    F = albedo[:, None] + (1 - albedo[:, None]) * ((1 - np.maximum(0, -dn)) ** 5)[None, :]
+    if trap_colour:
+        # a trap component at the reflected hit can move by 4e-4 when the
+        # point moves by 1e-7 (here: the radial normal against the oracle's
+        # analytic one), so the closed-form trap is taken at the oracle's own
+        # reflected hit, checked first against the closed-form intersection
+        Rb, Tb, sb = orc.object_frame(sc["objects"][1])
+        nrm = out["normal"][:, pix].T
+        dno = np.einsum("ij,ij->i", d, nrm)
+        rdo = d - 2 * dno[:, None] * nrm
+        qo = p + 4 * eps_s[:, None] * nrm
+        r = orc.trace_rays(sc["objects"][1]["fractal"], [], orc.object_march(mc, sb), (qo - Tb) @ Rb / sb, rdo @ Rb,
+                           eps0=eps_s / sb)
+        hpo = qo + (r["depth"] * sb)[:, None] * rdo
+        both = meets & clear & ((r["status"] & 7) >= 2)
+        assert np.abs(hpo[both] - hp[both]).max() < 1e-6
+        hp = np.where(both[:, None], hpo, hp)
+    albB = _trap_albedo(albedo, pal, np.array([_trap_c0((q - TB) / sBf, fr["max_iter"], fr["bailout2"])
+                                                for q in hp]).T)
+    c_r = _phong_closed(np.where(meets[:, None], NB, 0.0), L, -rd, albB, mc)
+    F = albA + (1 - albA) * ((1 - np.maximum(0, -dn)) ** 5)[None, :]
     ref = base + np.where(meets[None, :], mc["k_reflect"] * F * c_r, 0.0)
     flag = (out["status"][pix] & orc.FLAG_REFLECT_HIT) != 0
     assert np.array_equal(flag[clear], meets[clear])

@@ -60,14 +60,27 @@ def march(max_steps, eps_abs=0.0, eps_rel=0.0, normal_mode="tetra", shadow=False
 # term's f0 differs per channel.
 PHONG = {"shading": "phong", "k_specular": 0.5, "shininess": 40.0, "k_reflect": 0.1}
 PHONG_ALBEDO = f32v([0.9, 0.6, 0.3])
+# Orbit-trap colouring of the closest-hit shading (the colour parameters of
+# the Mandelbulb distance listing, read by the shader): per unit of the trap
+# components (min |x|, min |y|, min |z|, min |w|^2) the change of the albedo
+# (r, g, b); the builder's palette, since the paper's colouring is not given.
+TRAP_COLOUR = [f32v([-0.6, 0.2, 0.5]), f32v([0.3, -0.5, 0.2]), f32v([0.2, 0.3, -0.6]), f32v([-0.2, -0.2, -0.1])]
 
 
-def phong(mc):
-    """A march dict switched to the closest-hit shading."""
+def phong(mc, trap_colour=False):
+    """A march dict switched to the closest-hit shading (with the orbit-trap
+    palette when trap_colour is set)."""
     out = dict(mc)
     out.update({k: (f32(v) if isinstance(v, float) else v) for k, v in PHONG.items()})
     out["albedo"] = list(PHONG_ALBEDO)
+    if trap_colour:
+        out["trap_colour"] = [list(r) for r in TRAP_COLOUR]
     return out
+
+
+def job_scene(jb):
+    """A single render as a one-object scene with the identity placement."""
+    return scene(jb["camera"], [scene_object(jb["fractal"], jb.get("planes", ()))], jb["march"])
 
 
 def julia(c, max_iter, bailout2=256.0, bound_radius=0.0, degree=2):
