@@ -492,55 +492,12 @@ def render_scene(scene, pixels=None, samples=0):
             shadowed[idx[hit_k]] = True
         vis[lit[shadowed]] = 0.0
         status[lit[shadowed]] |= FLAG_SHADOWED
-    # orbit trap (R24) at the hit point, in the object's frame
+    h = np.nonzero(hit)[0]
+    colour = np.zeros((3, n))
     trap = np.zeros((4, n))
-    for k, ob in enumerate(scene["objects"]):
-        m = np.nonzero(best == k)[0]
-        if m.size:
-            R, T, s = object_frame(ob)
-            trap[:, m] = orbit_trap(ob["fractal"], (o[m] + depth[m, None] * d[m] - T) @ R / s).T
-    phong = mc.get("shading", "lambert") == "phong"
-    albedo = np.array(mc["albedo"], dtype=np.float64)
-    pal = np.array(mc.get("trap_colour", [[0.0] * 3] * 4), dtype=np.float64) if phong else np.zeros((4, 3))
-    alb = trap_albedo(albedo, pal, trap)                           # [3, n]
-    lam = mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0.0, ndl) * vis
-    colour = alb * lam[None, :]
-    if phong:
-        # R23: white Phong highlight (shadowed with the diffuse term), then one
-        # reflection bounce weighted by Schlick's Fresnel term with f0 = albedo
-        colour = colour + float(mc["k_specular"]) * _phong_spec(nrm, Ld, -d, ndl, float(mc["shininess"]))[None, :] * vis
-        h = np.nonzero(hit)[0]
-        eps_s = mc["eps_abs"] + mc["eps_rel"] * depth[h]
-        dn = np.einsum("ij,ij->i", d[h], nrm[h])
-        rd = d[h] - 2.0 * dn[:, None] * nrm[h]
-        q = o[h] + depth[h, None] * d[h] + 4.0 * eps_s[:, None] * nrm[h]
-        rt = np.full(h.size, np.inf)
-        rn = np.zeros((h.size, 3))
-        rtrap = np.zeros((4, h.size))
-        for ob in scene["objects"]:
-            R, T, s = object_frame(ob)
-            qo, rdo = (q - T) @ R / s, rd @ R
-            r = trace_rays(ob["fractal"], ob.get("planes", []), object_march(mc, s), qo, rdo, eps0=eps_s / s)
-            tw = r["depth"] * s
-            better = ((r["status"] & 7) >= STATUS_HIT) & (tw < rt)
-            rt[better] = tw[better]
-            rn[better] = r["normal"][better] @ R.T
-            if better.any():
-                bi = np.nonzero(better)[0]
-                rtrap[:, bi] = orbit_trap(ob["fractal"], qo[bi] + r["depth"][bi, None] * rdo[bi]).T
-        rhit = np.isfinite(rt)
-        rl = np.linalg.norm(rn, axis=1, keepdims=True)
-        rn = np.where(rl > 0, rn / np.where(rl > 0, rl, 1.0), rn)
-        rndl = rn @ Ld
-        ralb = trap_albedo(albedo, pal, rtrap)
-        c_r = ralb * (mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0.0, rndl))[None, :]
-        c_r = c_r + float(mc["k_specular"]) * _phong_spec(rn, Ld, -rd, rndl, float(mc["shininess"]))[None, :]
-        c_r = np.where(rhit[None, :], c_r, 0.0)
-        cos_i = np.maximum(0.0, -dn)
-        ah = alb[:, h]
-        F = ah + (1.0 - ah) * ((1.0 - cos_i) ** 5)[None, :]
-        colour[:, h] += float(mc["k_reflect"]) * F * c_r
-        status[h[rhit]] |= FLAG_REFLECT_HIT
+    colour[:, h], trap[:, h], rhit = shade_hits(scene, best[h], o[h] + depth[h, None] * d[h], d[h], nrm[h],
+                                                vis[h], mc["eps_abs"] + mc["eps_rel"] * depth[h])
+    status[h[rhit]] |= FLAG_REFLECT_HIT
     colour = np.where(hit[None, :], colour, 0.0)
     out = {"depth": depth, "normal": np.where(hit[None, :], nrm.T, 0.0), "colour": colour, "status": status,
            "object_id": best, "trap": trap}
@@ -548,8 +505,95 @@ def render_scene(scene, pixels=None, samples=0):
     return out
 
 
+def shade_hits(scene, object_ids, points, dirs, normals, vis, eps_s):
+    """Colour of scene hits (R11, R23, R24): object index [n], world hit
+    points [n, 3], unit ray directions [n, 3], unit normals [n, 3],
+    shadow-ray visibility [n] (0 or 1) and eps(t*) [n].  The albedo follows
+    the orbit trap of the hit point in its object's frame when a palette is
+    given (closest-hit shading only); Lambert's term, then with the
+    closest-hit shading the white highlight (shadowed with the diffuse term)
+    and the reflection bounce.  Returns colour [3, n], the traps [4, n] and
+    the reflected-hit flags [n] (all False under Lambert shading)."""
+    mc = scene["march"]
+    n = np.asarray(object_ids).size
+    pts = np.asarray(points, np.float64).reshape(n, 3)
+    d = np.asarray(dirs, np.float64).reshape(n, 3)
+    nrm = np.asarray(normals, np.float64).reshape(n, 3)
+    vis = np.asarray(vis, np.float64)
+    trap = np.zeros((4, n))
+    for k, ob in enumerate(scene["objects"]):
+        m = np.nonzero(np.asarray(object_ids) == k)[0]
+        if m.size:
+            R, T, s = object_frame(ob)
+            trap[:, m] = orbit_trap(ob["fractal"], (pts[m] - T) @ R / s).T
+    Ld = np.array(mc["light_dir"], dtype=np.float64)
+    Ld /= np.linalg.norm(Ld)
+    ndl = nrm @ Ld
+    phong = mc.get("shading", "lambert") == "phong"
+    albedo = np.array(mc["albedo"], dtype=np.float64)
+    pal = np.array(mc.get("trap_colour", [[0.0] * 3] * 4), dtype=np.float64) if phong else np.zeros((4, 3))
+    alb = trap_albedo(albedo, pal, trap)                           # [3, n]
+    colour = alb * (mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0.0, ndl) * vis)[None, :]
+    rhit = np.zeros(n, bool)
+    if phong:
+        # R23: white Phong highlight (shadowed with the diffuse term), then one
+        # reflection bounce weighted by Schlick's Fresnel term with f0 = albedo
+        colour = colour + float(mc["k_specular"]) * _phong_spec(nrm, Ld, -d, ndl, float(mc["shininess"]))[None, :] * vis
+        term, rhit = reflection_term(scene, pts, d, nrm, eps_s, alb)
+        colour = colour + term
+    return colour, trap, rhit
+
+
+def reflection_term(scene, points, dirs, normals, eps_s, albedo):
+    """The reflection bounce of the closest-hit shading (R23) for hits at
+    world points [n, 3] seen along unit dirs [n, 3], with unit normals
+    [n, 3], thresholds eps(t*) [n] and albedos [3, n]: the ray leaves
+    p* + 4 eps N along dir - 2 (dir . N) N against every object (threshold
+    eps(t*) + eps_rel s at distance s), and its first hit is shaded with
+    Lambert and the highlight (no shadow ray, 0 on a miss), weighted by
+    k_r and Schlick's F = albedo + (1 - albedo)(1 - max(0, -dir . N))^5.
+    Returns the term [3, n] and the reflected hit flags [n]."""
+    mc = scene["march"]
+    Ld = np.array(mc["light_dir"], dtype=np.float64)
+    Ld /= np.linalg.norm(Ld)
+    albedo0 = np.array(mc["albedo"], dtype=np.float64)
+    pal = np.array(mc.get("trap_colour", [[0.0] * 3] * 4), dtype=np.float64)
+    d = np.asarray(dirs, np.float64)
+    nrm = np.asarray(normals, np.float64)
+    n = d.shape[0]
+    dn = np.einsum("ij,ij->i", d, nrm)
+    rd = d - 2.0 * dn[:, None] * nrm
+    q = np.asarray(points, np.float64) + 4.0 * np.asarray(eps_s, np.float64)[:, None] * nrm
+    rt = np.full(n, np.inf)
+    rn = np.zeros((n, 3))
+    rtrap = np.zeros((4, n))
+    for ob in scene["objects"]:
+        R, T, s = object_frame(ob)
+        qo, rdo = (q - T) @ R / s, rd @ R
+        r = trace_rays(ob["fractal"], ob.get("planes", []), object_march(mc, s), qo, rdo, eps0=eps_s / s)
+        tw = r["depth"] * s
+        better = ((r["status"] & 7) >= STATUS_HIT) & (tw < rt)
+        rt[better] = tw[better]
+        rn[better] = r["normal"][better] @ R.T
+        if better.any():
+            bi = np.nonzero(better)[0]
+            rtrap[:, bi] = orbit_trap(ob["fractal"], qo[bi] + r["depth"][bi, None] * rdo[bi]).T
+    rhit = np.isfinite(rt)
+    rl = np.linalg.norm(rn, axis=1, keepdims=True)
+    rn = np.where(rl > 0, rn / np.where(rl > 0, rl, 1.0), rn)
+    rndl = rn @ Ld
+    ralb = trap_albedo(albedo0, pal, rtrap)
+    c_r = ralb * (mc["k_ambient"] + mc["k_diffuse"] * np.maximum(0.0, rndl))[None, :]
+    c_r = c_r + float(mc["k_specular"]) * _phong_spec(rn, Ld, -rd, rndl, float(mc["shininess"]))[None, :]
+    c_r = np.where(rhit[None, :], c_r, 0.0)
+    cos_i = np.maximum(0.0, -dn)
+    ah = np.asarray(albedo, np.float64)
+    F = ah + (1.0 - ah) * ((1.0 - cos_i) ** 5)[None, :]
+    return float(mc["k_reflect"]) * F * c_r, rhit
+
+
 def trap_albedo(albedo, palette, trap):
-    """Albedo of hits [3, n] coloured by their orbit traps [4, n] (R25): per
+    """Albedo of hits [3, n] coloured by their orbit traps [4, n] (R24): per
     channel albedo_c + sum_k palette[k][c] T_k, clamped to [0, 1]."""
     return np.clip(np.asarray(albedo, np.float64)[:, None] + np.asarray(palette, np.float64).T @ trap, 0.0, 1.0)
 

@@ -181,7 +181,7 @@ def test_two_ball_reflections(frt, orc):
 def test_overlap_scene_closest_hit_shading_and_trap(frt, orc, mode):
     sc = W.overlap_scene(width=200, height=150, normal_mode=mode)
     sc["march"] = W.phong(sc["march"])
-    g, o = _shaded_parity(frt, orc, sc, colour_ok=0.99)
+    g, o = _shaded_parity(frt, orc, sc, colour_ok=0.999)
     assert np.sum((g["status"] & 128) != 0) > 200
     # orbit trap at the GPU's own hit point, in the object's frame
     hit = np.nonzero(g["object_id"] >= 0)[0]
