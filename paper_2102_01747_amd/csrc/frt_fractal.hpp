@@ -120,13 +120,18 @@ struct JuliaOrbit {
 // multiplicative).
 // ---------------------------------------------------------------------------
 struct JuliaDegOrbit {
-    float a, b, e, w, m2, dz2;
-    int k;
+    // dz2 is kept as dm * 2^de with dm in [0.5, 1): a body multiplies it by
+    // p^2 |z|^(2(p-1)), up to about 2^120 at the largest accepted degree and
+    // bailout, so the product of a few bodies leaves float range long before
+    // the estimate it feeds stops mattering.
+    float a, b, e, w, m2, dm;
+    int k, de;
 
     __device__ __forceinline__ void init(float x, float y, float z) {
         a = x; b = y; e = z; w = 0.0f;
         m2 = fmaf(a, a, fmaf(b, b, e * e));
-        dz2 = 1.0f;
+        dm = 0.5f;
+        de = 1;
         k = 0;
     }
     // current orbit point (first three components) and |z|^2
@@ -154,7 +159,9 @@ struct JuliaDegOrbit {
         float na, nb, ne, nw, fac;
         map(P, na, nb, ne, nw, fac);
         a = na; b = nb; e = ne; w = nw;
-        dz2 *= fac;
+        const float prod = dm * fac;
+        dm = __builtin_amdgcn_frexp_mantf(prod);
+        de += __builtin_amdgcn_frexp_expf(prod);
         m2 = fmaf(a, a, fmaf(b, b, fmaf(e, e, w * w)));
         ++k;
         return !(m2 > P.bail2);
@@ -164,10 +171,13 @@ struct JuliaDegOrbit {
         float na, nb, ne, nw, fac;
         map(P, na, nb, ne, nw, fac);
         a = na; b = nb; e = ne; w = nw;
-        const float dn = dz2 * fac;
+        const float prod = dm * fac;
+        const float dmn = __builtin_amdgcn_frexp_mantf(prod);
+        const int den = de + __builtin_amdgcn_frexp_expf(prod);
         const float mn = fmaf(a, a, fmaf(b, b, fmaf(e, e, w * w)));
         const int kn = k + 1;
-        dz2 = live ? dn : dz2;
+        dm = live ? dmn : dm;
+        de = live ? den : de;
         m2 = live ? mn : m2;
         k = live ? kn : k;
         return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2)) & __builtin_amdgcn_ballot_w64(kn < P.max_iter);
@@ -177,7 +187,9 @@ struct JuliaDegOrbit {
         const bool esc = m2 > P.bail2;
         r.bodies = k;
         r.it = esc ? k - 1 : k;
-        r.d = m2 > 0.0f ? kQuarterLn2 * hw_log2(m2) * (m2 * hw_rsq(m2)) * hw_rsq(dz2) : 0.0f;
+        // 1 / sqrt(dm 2^de) = rsq(dm 2^(de & 1)) 2^-(de >> 1), the odd power folded into the mantissa
+        const float inv = ldexpf(hw_rsq(ldexpf(dm, de & 1)), -(de >> 1));
+        r.d = m2 > 0.0f ? kQuarterLn2 * hw_log2(m2) * (m2 * hw_rsq(m2)) * inv : 0.0f;
         return r;
     }
 };

@@ -69,6 +69,17 @@ def test_degree16_small_bailout(frt, orc):
     _full_parity(frt, orc, job)
 
 
+def test_degree16_largest_bailout(frt, orc):
+    """Degree 16 with the largest bailout2 the library accepts (181:
+    181^16 is just under 2^120).  One body then multiplies the squared
+    running derivative by up to 256 * 181^15, about 2^120, so a plain float
+    product overflows within two bodies; the kernels keep it as mantissa and
+    exponent, and the estimate must still agree with the FP64 oracle."""
+    job = W.julia_view(c=[-0.2, 0.6, 0.2, 0.2], degree=16, width=96, height=96, max_iter=12)
+    job["fractal"]["bailout2"] = 181.0
+    _full_parity(frt, orc, job)
+
+
 @pytest.fixture(scope="module")
 def degree_jobs():
     return W.julia_degree_batch()
