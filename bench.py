@@ -40,6 +40,10 @@ FP32_NONPACKED_PEAK_TFLOPS = 78.6   # the same without packed FP32, which this b
 #   one distance evaluation outside the bodies: 16 (sample point 6, estimate
 #   tail 6, step update and stop test 4).
 FLOP_PER_BODY = {"julia": 24.0, "bulb": 30.0}
+# Bytes the primary march must write: float depth + status byte per ray, and
+# float3 normal + float3 colour (zeros) per miss.
+PRIMARY_BYTES_PER_RAY = 5
+MISS_EXTRA_BYTES = 24
 FLOP_PER_EVAL = 16.0
 STAGES = ("primary_march", "normals", "shadow_march")
 
@@ -50,15 +54,21 @@ KERNEL_SOURCES = ("frt_trace.hip", "frt_fractal.hpp", "frt_math.hpp", "frt_ray.h
                   "frt_gradient.hpp")
 
 
-def kernel_sources_sha256():
-    """SHA-256 of the forward kernels' code: the sources with comments and
-    whitespace removed, so that an edit of a comment keeps the profiled
-    figures (the sources hold no string literal with a comment marker)."""
+# sources of the adjoint kernels, for the recorded FP64 work per backward call
+ADJOINT_SOURCES = ("frt_adjoint.hip", "frt_fractal.hpp", "frt_math.hpp", "frt_ray.hpp", "frt_job.hpp",
+                   "frt_internal.hpp")
+FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
+
+
+def kernel_sources_sha256(names=KERNEL_SOURCES):
+    """SHA-256 of kernel code: the sources with comments and whitespace
+    removed, so that an edit of a comment keeps the profiled figures (the
+    sources hold no string literal with a comment marker)."""
     import hashlib
     import re
 
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_2102_01747_amd", "csrc", name)) as fh:
             code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
         code = re.sub(r"//[^\n]*", " ", code)
@@ -184,7 +194,26 @@ def adjoint_leg(frt, dev, reps):
 
     t_fd = timed(fd_all)
     n = len(jobs)
-    return {"workload": "julia8_mandelbulb8_512x512_cut_plane", "renders": n,
+    # the adjoint kernels' FP64 work: hardware FP64 FLOP on active lanes per
+    # backward call, from the PMC profile of the same sources, over this run's
+    # backward time
+    roof = None
+    path = os.path.join(ROOT, "profiles", "adjoint_fp64.json")
+    if os.path.exists(path):
+        try:
+            with open(path) as fh:
+                pr = json.load(fh)
+            if (pr.get("workload") == "julia8_mandelbulb8_512x512_cut_plane"
+                    and pr.get("adjoint_sources_sha256") == kernel_sources_sha256(ADJOINT_SOURCES)):
+                fl = float(pr["hw_fp64_flop_per_call"])
+                ach = fl / (t_b * 1e-3) / 1e12
+                roof = {"bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "flop_per_call": fl,
+                        "flop_kind": "hardware FP64 on active lanes (SQ_INSTS_VALU_FLOPS_FP64 x 64 x VALUUtilization)",
+                        "traffic": pr.get("bytes_per_call")}
+        except (OSError, ValueError, KeyError):
+            roof = None
+    return {"workload": "julia8_mandelbulb8_512x512_cut_plane", "renders": n, "roofline": roof,
             "grads_per_s": n / ((t_f + t_b) * 1e-3), "forward_ms": t_f, "backward_ms": t_b,
             "backward_over_forward": t_b / t_f, "fd_renders_per_gradient": "2 x (8 Julia / 5 Mandelbulb parameters)",
             "fd_grads_per_s": n / (t_fd * 1e-3), "speedup_vs_fd": (t_fd) / (t_f + t_b),
@@ -318,9 +347,15 @@ def main():
     frt.render_batch(jobs, dev, outs=cframes, workspace=ws)
     torch.cuda.synchronize()
     flops = np.zeros(3)
+    misses = 0
     for f in cframes:
         flops += np.array(stage_flop("bulb", f["counters"].cpu().numpy().view(np.uint32)))
+        misses += int(((f["status"] & 7) < 2).sum())
     del cframes
+    # the primary march's algorithmic output: depth and status of every ray,
+    # plus the zero normal and colour of every miss (hits get theirs from the
+    # normal kernel); its reads are the job table only
+    out_bytes = PRIMARY_BYTES_PER_RAY * rays + MISS_EXTRA_BYTES * misses
 
     for _ in range(args.warmup):
         step()
@@ -396,7 +431,10 @@ def main():
                      "kernel": ("normal_kernel<%s>" if dom == "normals" else "march_kernel<%s>") % variant,
                      "stage": dom, "flop_per_launch": stages[dom]["flop"], "launch_ms": stages[dom]["ms"],
                      "peak_nonpacked_fp32": FP32_NONPACKED_PEAK_TFLOPS,
-                     "frac_of_nonpacked": achieved / FP32_NONPACKED_PEAK_TFLOPS},
+                     "frac_of_nonpacked": achieved / FP32_NONPACKED_PEAK_TFLOPS,
+                     "algorithmic_bytes": float(out_bytes) if dom == "primary_march" else None,
+                     "traffic_over_algorithmic": (traffic / out_bytes) if (traffic and dom == "primary_march")
+                     else None},
         "stages": stages,
         "hardware_fp32": hardware_fp32(hw_flop, stages[dom]["ms"]),
         "whole_path_tflops": float(flops.sum() / (ms_step * 1e-3) / 1e12),
