@@ -4,8 +4,9 @@ z <= 0.1, 15 orbit iterations, 1024 steps, eps = 2e-4 t, central normals.
 
 All 64 frames (530 M rays) are rendered in one batch call, traced as two
 groups: the 8 integer-power frames by the integer-power kernels and the 56
-real-power frames by the real-power kernels.  Four frames (two of each) are
-compared with the FP64 oracle on one pixel per 16x16 cell.  The
+real-power frames by the real-power kernels.  Five frames (0, 20, 45, 50
+and 63: three integer and two real powers) are compared with the FP64
+oracle on one pixel per 16x16 cell.  The
 adjoint with respect to n is checked against FP64 central differences on two
 frames at reduced resolution (same cameras), with a seeded N(0, 1) cotangent
 on the colour (L = sum w . colour).
