@@ -81,6 +81,9 @@ struct JuliaOrbit {
         return !(m2 > P.bail2);
     }
     __device__ __forceinline__ unsigned long long step(const OrbitParams& P, unsigned long long live_mask) {
+        // The body is short, so stopped lanes run it too and keep their
+        // estimate's inputs by three selects: cheaper here than switching
+        // the exec mask around it (the longer bodies below do that).
         const bool live = __builtin_amdgcn_inverse_ballot_w64(live_mask);
         const float pn = prod * m2;
         const float vv = fmaf(b, b, fmaf(e, e, w * w));
@@ -167,20 +170,19 @@ struct JuliaDegOrbit {
         return !(m2 > P.bail2);
     }
     __device__ __forceinline__ unsigned long long step(const OrbitParams& P, unsigned long long live_mask) {
-        const bool live = __builtin_amdgcn_inverse_ballot_w64(live_mask);
-        float na, nb, ne, nw, fac;
-        map(P, na, nb, ne, nw, fac);
-        a = na; b = nb; e = ne; w = nw;
-        const float prod = dm * fac;
-        const float dmn = __builtin_amdgcn_frexp_mantf(prod);
-        const int den = de + __builtin_amdgcn_frexp_expf(prod);
-        const float mn = fmaf(a, a, fmaf(b, b, fmaf(e, e, w * w)));
-        const int kn = k + 1;
-        dm = live ? dmn : dm;
-        de = live ? den : de;
-        m2 = live ? mn : m2;
-        k = live ? kn : k;
-        return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2)) & __builtin_amdgcn_ballot_w64(kn < P.max_iter);
+        // the body runs under the live lanes' exec mask: stopped lanes keep
+        // their state without selects
+        if (__builtin_amdgcn_inverse_ballot_w64(live_mask)) {
+            float na, nb, ne, nw, fac;
+            map(P, na, nb, ne, nw, fac);
+            a = na; b = nb; e = ne; w = nw;
+            const float prod = dm * fac;
+            dm = __builtin_amdgcn_frexp_mantf(prod);
+            de += __builtin_amdgcn_frexp_expf(prod);
+            m2 = fmaf(a, a, fmaf(b, b, fmaf(e, e, w * w)));
+            ++k;
+        }
+        return live_mask & __builtin_amdgcn_ballot_w64(!(m2 > P.bail2)) & __builtin_amdgcn_ballot_w64(k < P.max_iter);
     }
     __device__ __forceinline__ DEResult result(const OrbitParams& P) const {
         DEResult r;
@@ -268,16 +270,17 @@ struct BulbOrbit {
         }
     }
     __device__ __forceinline__ unsigned long long step(const OrbitParams& P, unsigned long long live_mask) {
-        const bool live = __builtin_amdgcn_inverse_ballot_w64(live_mask);
-        float nx, ny, nz, ndr;
-        map(P, nx, ny, nz, ndr);
-        wx = nx; wy = ny; wz = nz;
-        const float mn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
-        const int kn = k + 1;
-        dr = live ? ndr : dr;
-        m = live ? mn : m;
-        k = live ? kn : k;
-        return live_mask & __builtin_amdgcn_ballot_w64(!(mn > P.bail2)) & __builtin_amdgcn_ballot_w64(kn < P.max_iter);
+        // the body runs under the live lanes' exec mask: stopped lanes keep
+        // their state without selects
+        if (__builtin_amdgcn_inverse_ballot_w64(live_mask)) {
+            float nx, ny, nz, ndr;
+            map(P, nx, ny, nz, ndr);
+            wx = nx; wy = ny; wz = nz;
+            m = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+            dr = ndr;
+            ++k;
+        }
+        return live_mask & __builtin_amdgcn_ballot_w64(!(m > P.bail2)) & __builtin_amdgcn_ballot_w64(k < P.max_iter);
     }
     __device__ __forceinline__ bool body(const OrbitParams& P) {
         if constexpr (MODE == 0) {

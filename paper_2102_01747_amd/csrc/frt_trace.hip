@@ -402,37 +402,24 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                         phase = kMarch;
                     }
                 }
-                if (phase == kMarch) {   // Listing 3
-                    ++steps;
-                    if (!SHADOW) hit_it = de.it;
-                    if (d < fmaf(er, t, ea)) {
-                        if constexpr (SHADOW) {
-                            status = kFlagShadowed;
-                            phase = kDone;
-                        } else if (steps > 1) {
-                            // refine the root of g = d - eps on the bracket
-                            // [lt, t1] of the last two samples, g(lt) >= 0 > g(t1)
-                            status = kHit;
-                            lh -= fmaf(er, lt, ea);
-                            gb = d - fmaf(er, t, ea);
-                            t1 = t;
-                            rk = 0;
-                            if (refine_iters > 0 && t1 - lt > kRefineTol * fmaf(er, t1, ea)) {
-                                phase = kRefine;
-                                t = 0.5f * (lt + t1);
-                            } else {
-                                t = fmaf(-gb, __fdividef(t1 - lt, gb - lh), t1);   // secant on the bracket
-                                phase = kDone;
-                            }
-                        } else {
-                            status = kHit | kFlagUnrefined;
-                            phase = kDone;
-                        }
-                    } else {
-                        if constexpr (!SHADOW) {
-                            lt = t;
-                            lh = d;
-                        }
+                if (phase == kMarch || phase == kRefine) {
+                    // g = d - eps(t).  One bracket update serves the march
+                    // (Listing 3) and the bisection: a sample above the
+                    // eps-region becomes the bracket's left end lt (g(lt) =
+                    // lh >= 0), one below it the right end t1 (g(t1) = gb <
+                    // 0).  A march lane keeps t1 = the interval's end until
+                    // its first sample below, which ends the march.
+                    const bool ref = !SHADOW && phase == kRefine;
+                    const float g = d - fmaf(er, t, ea);
+                    const bool below = g < 0.0f;
+                    if (!ref) {
+                        ++steps;
+                        if (!SHADOW) hit_it = de.it;
+                    }
+                    if constexpr (!SHADOW) {
+                        if (below) { t1 = t; gb = g; } else { lt = t; lh = g; }
+                    }
+                    if (!ref && !below) {
                         t += fminf(d, clamp);
                         if (t > t1) {
                             status = SHADOW ? 0 : kMissTmax;
@@ -441,17 +428,22 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                             status = SHADOW ? kFlagShadowed : (kHitExhausted | kFlagUnrefined);
                             phase = kDone;
                         }
-                    }
-                } else if (!SHADOW && phase == kRefine) {   // shadow rays stop at their first hit
-                    // bisection step on [lt, t1]; t is the midpoint just evaluated
-                    const float fx = d - fmaf(er, t, ea);
-                    if (fx < 0.0f) { t1 = t; gb = fx; } else { lt = t; lh = fx; }
-                    ++rk;
-                    if (rk >= refine_iters || t1 - lt <= kRefineTol * fmaf(er, t1, ea)) {
-                        t = fmaf(-gb, __fdividef(t1 - lt, gb - lh), t1);   // secant on the final bracket
+                    } else if (SHADOW || (!ref && steps == 1)) {
+                        // shadow rays stop at their first hit; a primary ray
+                        // whose first sample is inside has no bracket
+                        status = SHADOW ? kFlagShadowed : (kHit | kFlagUnrefined);
                         phase = kDone;
                     } else {
-                        t = 0.5f * (lt + t1);
+                        // the bracket [lt, t1] holds a root of g: bisect it
+                        // down to eps / 32, then one secant step
+                        if (ref) ++rk; else { status = kHit; rk = 0; }
+                        if (rk < refine_iters && t1 - lt > kRefineTol * fmaf(er, t1, ea)) {
+                            phase = kRefine;
+                            t = 0.5f * (lt + t1);
+                        } else {
+                            t = fmaf(-gb, __fdividef(t1 - lt, gb - lh), t1);
+                            phase = kDone;
+                        }
                     }
                 }
                 if (phase == kCut || phase == kMarch || phase == kRefine) {
