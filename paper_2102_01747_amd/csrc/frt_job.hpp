@@ -3,6 +3,7 @@
 // precomputed once per render) and read by the kernels.
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 namespace frt {
@@ -127,11 +128,28 @@ struct alignas(256) WorkspaceHeader {
     unsigned long long adj_queue[2];             // tile groups claimed by the adjoint kernels (per kind)
     unsigned long long total_rays;
     int32_t n_jobs;
-    int32_t pad[(1024 - 16 * kNumVariants - 28) / 4];
+    int32_t pad0[(512 - 16 * kNumVariants - 28) / 4];
+    // per-stage trip statistics of the march kernels, summed over their
+    // waves; written only by a build with FRT_TRIP_COUNTERS defined (the host
+    // zeroes the header's first KiB on every call): [stage * 16 + k], stage
+    // 0 primary and 1 shadow march, k as in TripCounter
+    unsigned long long trips[32];
+    int32_t pad1[(1024 - 512 - 256) / 4];
     // [(variant * 2 + stage) * kQueueSlots + slot][0]: chunks claimed from
     // that slot's share (stage 0 primary march, 1 shadow march)
     unsigned long long queue[kNumVariants * 2 * kQueueSlots][32];
 };
+enum TripCounter {
+    kTripLoops = 0,      // trips round the wave's outer loop
+    kTripRefills,        // trips that wrote finished rays and refilled lanes
+    kTripBodyIters,      // iterations of the orbit loop (wave level)
+    kTripSteps,          // trips whose step path had a lane to step
+    kTripClaims,         // claim attempts on the work queue
+    kTripLiveLanes,      // live lanes summed over orbit-loop iterations (orbit bodies)
+    kTripStepLanes,      // lanes summed over step paths (distance estimates used)
+    kTripCount
+};
+static_assert(offsetof(WorkspaceHeader, trips) == 512, "trip counters at byte 512 of the header");
 static_assert(sizeof(WorkspaceHeader) == 1024 + kNumVariants * 2 * kQueueSlots * 256,
               "workspace header: 1 KiB of fields, then the claim counters");
 

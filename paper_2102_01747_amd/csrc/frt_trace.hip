@@ -32,6 +32,15 @@
 
 namespace frt {
 
+// FRT_TRIP_COUNTERS: a measurement build that counts, per march stage, the
+// wave-level trips, orbit-loop iterations, step paths and claims (summed
+// into the workspace header at each wave's exit); off in the product build.
+#ifdef FRT_TRIP_COUNTERS
+#define FRT_TRIP_ADD(k, v) (trip_c[k] += (v))
+#else
+#define FRT_TRIP_ADD(k, v) ((void)0)
+#endif
+
 // Bisection stops once the root bracket is narrower than eps(t) / 32 (then one
 // secant step on the final bracket).  A coarser bracket keeps the depth within
 // tolerance but moves the normal taps with it; the bisection also picks the
@@ -115,6 +124,9 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
         r_end = hdr->range[VAR][1];
     }
     unsigned long long q_next = 0, q_end = 0;   // wave-uniform window of claimed rays
+#ifdef FRT_TRIP_COUNTERS
+    unsigned long long trip_c[kTripCount] = {};
+#endif
     bool drained = false;
     // A wave's first claim is chunk number (its index in the grid), taken
     // without a counter.  The chunks after the grid's first n_waves are
@@ -130,6 +142,7 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
     unsigned spent = 0u;   // slots whose share is spent (wave-uniform)
     bool first_claim = true;
     auto claim = [&]() -> unsigned long long {   // the chunk's first ray, or r_end
+        FRT_TRIP_ADD(kTripClaims, 1);
         if (first_claim) {
             first_claim = false;
             return min(r_begin + first_chunk * static_cast<unsigned long long>(chunk), r_end);
@@ -182,12 +195,21 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
 
     for (;;) {
         // ------------------------------------------ finished rays + refill
+        FRT_TRIP_ADD(kTripLoops, 1);
         const unsigned long long m_busy = __ballot(phase == kCut || phase == kMarch || phase == kRefine);
         const unsigned long long m_done = __ballot(phase == kDone);
         const bool exhausted = drained && tmask == 0ull;
-        if (m_busy == 0ull && m_done == 0ull && exhausted) break;
+        if (m_busy == 0ull && m_done == 0ull && exhausted) {
+#ifdef FRT_TRIP_COUNTERS
+            if (__lane_id() == 0) {
+                for (int k = 0; k < kTripCount; ++k) atomicAdd(&hdr->trips[(SHADOW ? 16 : 0) + k], trip_c[k]);
+            }
+#endif
+            break;
+        }
         const int waiting = __popcll(m_done) + (exhausted ? 0 : __popcll(__ballot(phase == kIdle)));
         if (m_busy == 0ull || waiting >= rare_lanes) {
+            FRT_TRIP_ADD(kTripRefills, 1);
             const bool one_job = BATCH && __ballot(phase == kDone && jb != cur.j) == 0ull;
             // when the finished lanes all belong to the cursor's job (the
             // usual case) its output pointers come through scalar loads
@@ -382,9 +404,21 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
             const int keep = __popcll(live) < orbit_lanes ? 1 : orbit_lanes;
             int b = 0;
             do {
+                FRT_TRIP_ADD(kTripBodyIters, 1);
+                FRT_TRIP_ADD(kTripLiveLanes, __popcll(live));
                 live = orb.step(P, live);
             } while (++b < kMaxBodiesPerTrip && __popcll(live) >= keep);
         }
+#ifdef FRT_TRIP_COUNTERS
+        {
+            const unsigned long long m_step =
+                __ballot(!__builtin_amdgcn_inverse_ballot_w64(live) && (phase == kCut || phase == kMarch || phase == kRefine));
+            if (m_step != 0ull) {
+                FRT_TRIP_ADD(kTripSteps, 1);
+                FRT_TRIP_ADD(kTripStepLanes, __popcll(m_step));
+            }
+        }
+#endif
         if (!__builtin_amdgcn_inverse_ballot_w64(live) && (phase == kCut || phase == kMarch || phase == kRefine)) {
             {
                 const DEResult de = orb.result(P);
