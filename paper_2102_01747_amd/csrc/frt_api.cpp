@@ -383,6 +383,9 @@ struct Staging {
     bool pending = false;
 };
 constexpr int kStageSlots = 8;
+// first size of a staging buffer: the header and a few dozen jobs with their
+// adjoint entries
+constexpr size_t kStageMinBytes = size_t(64) << 10;
 std::mutex g_stage_mu;
 Staging g_stage[kStageSlots];
 int g_stage_next = 0;
@@ -425,12 +428,16 @@ frt_status upload_parts(const void* const* parts, const size_t* sizes, int n_par
         sg.pending = false;
     }
     if (sg.bytes < bytes) {
+        // grow by powers of two from kStageMinBytes: freeing pinned memory
+        // waits for the device, so a slot should rarely need it again
+        size_t cap = kStageMinBytes;
+        while (cap < bytes) cap *= 2;
         if (sg.host) (void)hipHostFree(sg.host);
         sg.host = nullptr;
         sg.bytes = 0;
-        e = hipHostMalloc(&sg.host, bytes, hipHostMallocDefault);
+        e = hipHostMalloc(&sg.host, cap, hipHostMallocDefault);
         if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
-        sg.bytes = bytes;
+        sg.bytes = cap;
     }
     if (!sg.done) {
         e = hipEventCreateWithFlags(&sg.done, hipEventDisableTiming);

@@ -26,6 +26,9 @@ NAMES = ("trips", "refills", "body_iterations", "step_paths", "claims", "live_la
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--build", action="store_true", help="build libfrt_trips.so first")
+    ap.add_argument("--check", action="store_true",
+                    help="render with the per-pixel counter planes too and require that the lanes the trip "
+                         "counters saw equal the planes' estimates and orbit bodies (exit status 1 otherwise)")
     args = ap.parse_args()
     from paper_2102_01747_amd import _build
 
@@ -44,13 +47,20 @@ def main():
     frt.lib()
     dev = torch.device("cuda:0")
     jobs = W.bulb_views()
-    frames = [frt.alloc_frame(j, dev) for j in jobs]
+    frames = [frt.alloc_frame(j, dev, counters=args.check) for j in jobs]
     ws = frt.alloc_workspace(len(jobs), dev)
     for _ in range(2):
         frt.render_batch(jobs, dev, outs=frames, workspace=ws)
     torch.cuda.synchronize()
     raw = ws[512:768].cpu().numpy().view(np.uint64)
     rays = sum(j["camera"]["width"] * j["camera"]["height"] for j in jobs)
+    planes = None
+    if args.check:
+        # counter planes 1, 2: primary estimates and bodies; 6, 7: shadow ones
+        planes = np.zeros(8, np.int64)
+        for f in frames:
+            planes += f["counters"].cpu().numpy().view(np.uint32).astype(np.int64).sum(axis=1)
+    ok = True
     for stage, base in (("primary_march", 0), ("shadow_march", 16)):
         c = dict(zip(NAMES, (int(v) for v in raw[base:base + len(NAMES)])))
         c["stage"] = stage
@@ -59,7 +69,14 @@ def main():
         c["orbit_loop_lane_use"] = c["live_lane_iterations"] / (64.0 * c["body_iterations"]) if c["body_iterations"] else 0.0
         c["lanes_per_step_path"] = c["step_lanes"] / c["step_paths"] if c["step_paths"] else 0.0
         c["body_iterations_per_trip"] = c["body_iterations"] / c["trips"] if c["trips"] else 0.0
+        if planes is not None:
+            est, bod = (planes[1], planes[2]) if base == 0 else (planes[6], planes[7])
+            c["plane_estimates"], c["plane_bodies"] = int(est), int(bod)
+            c["check"] = bool(c["step_lanes"] == est and c["live_lane_iterations"] == bod)
+            ok &= c["check"]
         print(json.dumps(c), flush=True)
+    if not ok:
+        raise SystemExit(1)
 
 
 if __name__ == "__main__":

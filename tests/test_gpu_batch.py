@@ -227,3 +227,28 @@ def test_every_ray_claimed_under_any_launch_shape(frt, block, chunk):
             assert torch.equal(f[plane], g[plane]), (k, plane)
     assert not (single["status"] == 255).any() and not torch.isnan(single["depth"]).any()
     assert torch.equal(single["depth"], ref[3]["depth"])
+
+
+def test_trip_counters_match_the_counter_planes():
+    """The measurement build's trip counters (FRT_TRIP_COUNTERS) against the
+    per-pixel counter planes of the same renders: the lanes that took a
+    step path must equal the distance estimates, and the live lanes of the
+    orbit loop the orbit bodies, exactly, for the primary and the shadow
+    march of the eight 1080p views.  Run in a child process, which loads
+    libfrt_trips.so in place of libfrt.so."""
+    import json
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if not os.path.exists(os.path.join(root, "paper_2102_01747_amd", "libfrt_trips.so")):
+        pytest.skip("libfrt_trips.so not built")
+    res = subprocess.run([sys.executable, "-m", "paper_2102_01747_amd.trip_counts", "--check"], cwd=root,
+                         capture_output=True, text=True, timeout=240)
+    print(res.stdout, res.stderr[-2000:])
+    stages = [json.loads(l) for l in res.stdout.splitlines() if l.startswith("{")]
+    assert res.returncode == 0 and len(stages) == 2
+    for st in stages:
+        assert st["check"], st
+        assert 0.5 < st["orbit_loop_lane_use"] <= 1.0
