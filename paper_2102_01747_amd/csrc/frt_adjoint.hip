@@ -428,6 +428,34 @@ __device__ __forceinline__ void flush(const AdjointArgs& a, int j, float (&acc)[
 // Tiles per claim of the adjoint's counter.
 constexpr unsigned kAdjTiles = 4;
 
+// The surface-hit gradient of one queued pixel of job J (its index in the
+// job's planes); adds into acc and writes the per-pixel slots of its kind.
+template <int KIND>
+__device__ __forceinline__ void surface_item(const JobDev& J, const AdjointJob& A, long long p,
+                                             float (&acc)[kGradSlots]) {
+    const long long NP = J.npix;
+    const int py = static_cast<int>(p / J.width), px = static_cast<int>(p - static_cast<long long>(py) * J.width);
+    const bool lit = !(J.status[p] & kFlagShadowed);
+    const float gd = A.g_depth ? A.g_depth[p] : 0.0f;
+    const OrbitParams P = orbit_params(J);
+    if constexpr (KIND == kJulia) {
+        float pa[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        surface_hit_grad<kJulia, 4>(J, A, P, p, NP, lit, px, py, J.depth[p], gd, pa);
+        drop_nonfinite(pa);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[s] += pa[s];
+        if (A.g_pixel) {
+            for (int s = 0; s < 4; ++s) A.g_pixel[s * NP + p] = pa[s];
+        }
+    } else {
+        float pa[1] = {0.0f};
+        surface_hit_grad<kBulb, 1>(J, A, P, p, NP, lit, px, py, J.depth[p], gd, pa);
+        drop_nonfinite(pa);
+        acc[4] += pa[0];
+        if (A.g_pixel) A.g_pixel[4 * NP + p] = pa[0];
+    }
+}
+
 // One instantiation per fractal kind (the two tangent sets differ in size);
 // each drains the 64-ray tiles of its kind's jobs, [range[KIND][0],
 // range[KIND][1]) of the ray index space, kAdjTiles at a time.  A wave's
@@ -436,6 +464,13 @@ constexpr unsigned kAdjTiles = 4;
 // device-scope atomics per microsecond, so a claim per tile, and all waves
 // claiming at the start, would queue on it).  A tile lies inside one job,
 // found through the wave's job cursor.
+//
+// A tile's cut-face pixels take their closed form at once.  Its surface hits,
+// the FP64 orbit with tangents that holds most of the work, are queued in a
+// per-wave LDS list instead and evaluated 64 at a time, one per lane, so
+// misses and background pixels do not idle lanes through that work.  The
+// list holds one job's pixels: it is drained when the job changes (and at
+// the end), before the job's partial sums are flushed.
 template <int KIND>
 __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHeader* __restrict__ hdr) {
     const unsigned long long r0 = hdr->range[KIND][0];
@@ -446,6 +481,23 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHe
 #pragma unroll
     for (int s = 0; s < kGradSlots; ++s) acc[s] = 0.0f;
     int cur = -1;   // caller's index of the job the partial sums belong to (uniform across the wave)
+    int qj = -1;    // table index of the queued pixels' job (uniform)
+    int qn = 0;     // queued surface hits (uniform, < 64 between tiles)
+    __shared__ int queue_lds[4][128];
+    int* q = queue_lds[threadIdx.x >> 6];
+    // evaluate the first n (<= 64) queued pixels, then move the rest down
+    auto drain = [&](int n) {
+        const JobDev& J = a.jobs[qj];
+        const AdjointJob& A = a.ajobs[qj];
+        const int item = lane < n ? q[lane] : 0;
+        const int rest = qn - n;   // < 64
+        const int moved = lane < rest ? q[n + lane] : 0;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) q[lane] = moved;
+        __builtin_amdgcn_wave_barrier();
+        qn = rest;
+        if (lane < n) surface_item<KIND>(J, A, item, acc);
+    };
     JobCursor jc;
     const unsigned long long n_waves = static_cast<unsigned long long>(gridDim.x) * (blockDim.x >> 6);
     unsigned long long grp =
@@ -463,6 +515,10 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHe
             const unsigned long long g0 = r0 + (t << 6);
             job_seek<true>(a.jobs, a.jobs[0], n_jobs, g0, jc);
             const int j = jc.j;
+            if (j != qj) {
+                while (qn > 0) drain(min(qn, 64));
+                qj = j;
+            }
             const JobDev& J = a.jobs[j];
             const AdjointJob& A = a.ajobs[j];
             if (A.out_index != cur) {
@@ -471,62 +527,59 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHe
             }
             int px, py;
             const bool in = tile_pixel(J, static_cast<long long>(g0 - jc.begin) + lane, px, py);
-            if (!in) continue;
             const long long NP = J.npix;
             const long long p = static_cast<long long>(py) * J.width + px;
-            const int st = J.status[p];
-            const int cls = st & 7;
-            const bool smooth = cls == kHitCut || (cls == kHit && !(st & kFlagUnrefined));
-            if (A.g_pixel) {
-                for (int s = 0; s < kGradSlots; ++s) A.g_pixel[s * NP + p] = 0.0f;
-            }
-            if (!smooth) continue;
-            const bool lit = !(st & kFlagShadowed);
-            const float gd = A.g_depth ? A.g_depth[p] : 0.0f;
-            bool any = gd != 0.0f;
-            if (A.g_colour) any = any || A.g_colour[p] != 0.0f || A.g_colour[NP + p] != 0.0f || A.g_colour[2 * NP + p] != 0.0f;
-            if (A.g_normal) any = any || A.g_normal[p] != 0.0f || A.g_normal[NP + p] != 0.0f || A.g_normal[2 * NP + p] != 0.0f;
-            if (!any) continue;   // nothing flows into this pixel
-            if (cls == kHitCut) {
-                // entry plane as the forward pass found it (float32 ray)
-                float dx, dy, dz;
-                primary_dir(J, px, py, dx, dy, dz);
-                float lo, hi;
-                int e;
-                const bool ok = ray_interval(J, J.eye[0], J.eye[1], J.eye[2], dx, dy, dz, J.eps_abs, lo, hi, e);
-                if (ok && e >= 0) {
-                    float pa[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                    cut_face_grad(J, A, p, NP, lit, e, px, py, gd, pa);
-                    drop_nonfinite(pa);
-    #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        if (e == 0) acc[5 + s] += pa[s]; else acc[9 + s] += pa[s];
-                    }
-                    if (A.g_pixel) {
-                        for (int s = 0; s < 4; ++s) A.g_pixel[(5 + 4 * e + s) * NP + p] = pa[s];
+            bool surf = false;
+            if (in) {
+                const int st = J.status[p];
+                const int cls = st & 7;
+                const bool smooth = cls == kHitCut || (cls == kHit && !(st & kFlagUnrefined));
+                bool any = false;
+                if (smooth) {
+                    any = A.g_depth && A.g_depth[p] != 0.0f;
+                    if (A.g_colour) any = any || A.g_colour[p] != 0.0f || A.g_colour[NP + p] != 0.0f || A.g_colour[2 * NP + p] != 0.0f;
+                    if (A.g_normal) any = any || A.g_normal[p] != 0.0f || A.g_normal[NP + p] != 0.0f || A.g_normal[2 * NP + p] != 0.0f;
+                }
+                surf = smooth && any && cls == kHit;
+                if (A.g_pixel) {
+                    // a queued pixel writes its own kind's slots later
+                    for (int s = 0; s < kGradSlots; ++s) {
+                        const bool own = KIND == kJulia ? s < 4 : s == 4;
+                        if (!(surf && own)) A.g_pixel[s * NP + p] = 0.0f;
                     }
                 }
-            } else {
-                const OrbitParams P = orbit_params(J);
-                if constexpr (KIND == kJulia) {
-                    float pa[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                    surface_hit_grad<kJulia, 4>(J, A, P, p, NP, lit, px, py, J.depth[p], gd, pa);
-                    drop_nonfinite(pa);
-    #pragma unroll
-                    for (int s = 0; s < 4; ++s) acc[s] += pa[s];
-                    if (A.g_pixel) {
-                        for (int s = 0; s < 4; ++s) A.g_pixel[s * NP + p] = pa[s];
+                if (smooth && any && cls == kHitCut) {
+                    // entry plane as the forward pass found it (float32 ray)
+                    const bool lit = !(st & kFlagShadowed);
+                    const float gd = A.g_depth ? A.g_depth[p] : 0.0f;
+                    float dx, dy, dz;
+                    primary_dir(J, px, py, dx, dy, dz);
+                    float lo, hi;
+                    int e;
+                    const bool ok = ray_interval(J, J.eye[0], J.eye[1], J.eye[2], dx, dy, dz, J.eps_abs, lo, hi, e);
+                    if (ok && e >= 0) {
+                        float pa[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                        cut_face_grad(J, A, p, NP, lit, e, px, py, gd, pa);
+                        drop_nonfinite(pa);
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            if (e == 0) acc[5 + s] += pa[s]; else acc[9 + s] += pa[s];
+                        }
+                        if (A.g_pixel) {
+                            for (int s = 0; s < 4; ++s) A.g_pixel[(5 + 4 * e + s) * NP + p] = pa[s];
+                        }
                     }
-                } else {
-                    float pa[1] = {0.0f};
-                    surface_hit_grad<kBulb, 1>(J, A, P, p, NP, lit, px, py, J.depth[p], gd, pa);
-                    drop_nonfinite(pa);
-                    acc[4] += pa[0];
-                    if (A.g_pixel) A.g_pixel[4 * NP + p] = pa[0];
                 }
             }
+            // append this tile's surface hits to the queue
+            const unsigned long long m = __ballot(surf);
+            if (surf) q[qn + static_cast<int>(lane_rank(m))] = static_cast<int>(p);
+            __builtin_amdgcn_wave_barrier();
+            qn += __popcll(m);
+            if (qn >= 64) drain(64);
         }
     }
+    while (qn > 0) drain(min(qn, 64));
     if (cur >= 0) flush(a, cur, acc);
 }
 
