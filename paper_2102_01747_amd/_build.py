@@ -34,18 +34,19 @@ SANITIZE_HOST = "-O1 -g -Xarch_host -fsanitize=address -Xarch_host -fsanitize=un
                 "-Xarch_host -fno-sanitize-recover=undefined -Xarch_host -fno-omit-frame-pointer -shared-libsan"
 
 
-# The measurement build with the march kernels' trip counters (see
-# frt_trace.hip); it loads like libfrt.so through FRT_LIB_PATH.
-TRIPS_LIB = os.path.join(PKG, "libfrt_trips.so")
+# The instrumented build: the march kernels' trip counters and the kernels'
+# index checks (FRT_TRIP_COUNTERS, FRT_DEBUG_CHECKS; see frt_job.hpp); it
+# loads like libfrt.so through FRT_LIB_PATH.
+INSTR_LIB = os.path.join(PKG, "libfrt_instr.so")
 
 
-def build(verbose: bool = False, sanitize: bool = False, out: str = None, trip_counters: bool = False) -> str:
+def build(verbose: bool = False, sanitize: bool = False, out: str = None, instrument: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    dest = out or (TRIPS_LIB if trip_counters else LIB)
+    dest = out or (INSTR_LIB if instrument else LIB)
     tmp = dest + ".tmp"
     opt = SANITIZE_HOST.split() if sanitize else ["-O3"]
-    if trip_counters:
-        opt = opt + ["-DFRT_TRIP_COUNTERS"]
+    if instrument:
+        opt = opt + ["-DFRT_TRIP_COUNTERS", "-DFRT_DEBUG_CHECKS"]
     cmd = [hipcc(), "--offload-arch=" + ARCH] + opt + ["-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-I", INCLUDE, "-I", CSRC] + srcs + ["-o", tmp]

@@ -489,6 +489,10 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHe
     auto drain = [&](int n) {
         const JobDev& J = a.jobs[qj];
         const AdjointJob& A = a.ajobs[qj];
+        if (!FRT_CHECK(hdr, n >= 1 && n <= 64 && n <= qn && qn < 128, kCheckList)) {
+            qn = 0;   // a list out of its bounds: dropped
+            return;
+        }
         const int item = lane < n ? q[lane] : 0;
         const int rest = qn - n;   // < 64
         const int moved = lane < rest ? q[n + lane] : 0;
@@ -496,7 +500,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHe
         if (lane < rest) q[lane] = moved;
         __builtin_amdgcn_wave_barrier();
         qn = rest;
-        if (lane < n) surface_item<KIND>(J, A, item, acc);
+        if (lane < n && FRT_CHECK(hdr, item >= 0 && item < J.npix, kCheckPixel)) surface_item<KIND>(J, A, item, acc);
     };
     JobCursor jc;
     const unsigned long long n_waves = static_cast<unsigned long long>(gridDim.x) * (blockDim.x >> 6);
@@ -514,6 +518,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHe
         for (unsigned long long t = t0; t < t1; ++t) {
             const unsigned long long g0 = r0 + (t << 6);
             job_seek<true>(a.jobs, a.jobs[0], n_jobs, g0, jc);
+            if (!FRT_CHECK(hdr, jc.j >= 0 && jc.j < n_jobs, kCheckJob) ||
+                !FRT_CHECK(hdr, g0 >= jc.begin && g0 + 64ull <= jc.end, kCheckRay)) continue;
             const int j = jc.j;
             if (j != qj) {
                 while (qn > 0) drain(min(qn, 64));
@@ -530,7 +536,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHe
             const long long NP = J.npix;
             const long long p = static_cast<long long>(py) * J.width + px;
             bool surf = false;
-            if (in) {
+            if (in && FRT_CHECK(hdr, p >= 0 && p < NP, kCheckPixel)) {
                 const int st = J.status[p];
                 const int cls = st & 7;
                 const bool smooth = cls == kHitCut || (cls == kHit && !(st & kFlagUnrefined));
@@ -573,7 +579,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs a, WorkspaceHe
             }
             // append this tile's surface hits to the queue
             const unsigned long long m = __ballot(surf);
-            if (surf) q[qn + static_cast<int>(lane_rank(m))] = static_cast<int>(p);
+            if (surf && FRT_CHECK(hdr, qn + static_cast<int>(lane_rank(m)) < 128, kCheckList))
+                q[qn + static_cast<int>(lane_rank(m))] = static_cast<int>(p);
             __builtin_amdgcn_wave_barrier();
             qn += __popcll(m);
             if (qn >= 64) drain(64);

@@ -134,7 +134,10 @@ struct alignas(256) WorkspaceHeader {
     // zeroes the header's first KiB on every call): [stage * 16 + k], stage
     // 0 primary and 1 shadow march, k as in TripCounter
     unsigned long long trips[32];
-    int32_t pad1[(1024 - 512 - 256) / 4];
+    // index checks of a build with FRT_DEBUG_CHECKS defined: bit k set when
+    // check k (CheckBit) failed somewhere; the failing item was skipped
+    unsigned long long checks;
+    int32_t pad1[(1024 - 512 - 256 - 8) / 4];
     // [(variant * 2 + stage) * kQueueSlots + slot][0]: chunks claimed from
     // that slot's share (stage 0 primary march, 1 shadow march)
     unsigned long long queue[kNumVariants * 2 * kQueueSlots][32];
@@ -149,7 +152,23 @@ enum TripCounter {
     kTripStepLanes,      // lanes summed over step paths (distance estimates used)
     kTripCount
 };
+enum CheckBit {
+    kCheckRay = 0,     // a claimed ray index outside its group or its job
+    kCheckPixel = 1,   // a pixel index outside its job's planes
+    kCheckJob = 2,     // a job-table index outside the table
+    kCheckList = 3,    // an LDS list or slot index outside its array
+};
 static_assert(offsetof(WorkspaceHeader, trips) == 512, "trip counters at byte 512 of the header");
+static_assert(offsetof(WorkspaceHeader, checks) == 768, "check bits at byte 768 of the header");
+
+// FRT_CHECK(hdr, cond, bit): true when cond holds.  In a build with
+// FRT_DEBUG_CHECKS a failure sets the bit in hdr->checks (and the caller
+// skips the item); otherwise the check compiles away.
+#ifdef FRT_DEBUG_CHECKS
+#define FRT_CHECK(hdr, cond, bit) ((cond) ? true : (atomicOr(&(hdr)->checks, 1ull << (bit)), false))
+#else
+#define FRT_CHECK(hdr, cond, bit) true
+#endif
 static_assert(sizeof(WorkspaceHeader) == 1024 + kNumVariants * 2 * kQueueSlots * 256,
               "workspace header: 1 KiB of fields, then the claim counters");
 

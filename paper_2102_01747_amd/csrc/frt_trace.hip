@@ -213,6 +213,10 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
             const bool one_job = BATCH && __ballot(phase == kDone && jb != cur.j) == 0ull;
             // when the finished lanes all belong to the cursor's job (the
             // usual case) its output pointers come through scalar loads
+            if (phase == kDone && !FRT_CHECK(hdr, jb >= 0 && jb < n_jobs && pix >= 0 &&
+                                                  pix < job_ref<BATCH>(jobs, job1, jb).npix, kCheckPixel)) {
+                phase = kIdle;   // a finished ray whose pixel lies outside its job: not written
+            }
             if (phase == kDone) {
                 const JobDev& J = job_ref<BATCH>(jobs, job1, jb);
                 if constexpr (!SHADOW) {
@@ -243,13 +247,20 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                 }
                 // this round's rays all lie in the cursor's job
                 job_seek<BATCH>(jobs, job1, n_jobs, q_next, cur);
+                if (!FRT_CHECK(hdr, cur.j >= 0 && cur.j < n_jobs, kCheckJob) ||
+                    !FRT_CHECK(hdr, q_next >= cur.begin && q_next < cur.end && q_end <= r_end, kCheckRay)) {
+                    drained = true;
+                    break;
+                }
                 const unsigned rank = lane_rank(idle);
                 const unsigned long long avail = min(q_end, cur.end) - q_next;
                 const int j = cur.j;
                 const JobDev& J = job_ref<BATCH>(jobs, job1, j);
                 int px, py;
                 if (phase == kIdle && rank < avail &&
-                    tile_pixel(J, static_cast<long long>(q_next + rank - cur.begin), px, py)) {
+                    FRT_CHECK(hdr, static_cast<long long>(q_next + rank - cur.begin) < J.ray_count, kCheckRay) &&
+                    tile_pixel(J, static_cast<long long>(q_next + rank - cur.begin), px, py) &&
+                    FRT_CHECK(hdr, static_cast<long long>(py) * J.width + px < J.npix, kCheckPixel)) {
                     const int p = py * J.width + px;
                     float lo, hi;
                     bool go = false;
@@ -319,6 +330,11 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                     tile_g = q_next;
                     q_next += 64ull;
                     job_seek<BATCH>(jobs, job1, n_jobs, tile_g, cur);
+                    if (!FRT_CHECK(hdr, cur.j >= 0 && cur.j < n_jobs, kCheckJob) ||
+                        !FRT_CHECK(hdr, tile_g >= cur.begin && tile_g + 64ull <= cur.end && tile_g < r_end, kCheckRay)) {
+                        drained = true;
+                        break;
+                    }
                     const JobDev& J = job_ref<BATCH>(jobs, job1, cur.j);
                     int px, py;
                     bool cast = false;
@@ -515,11 +531,14 @@ __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ 
          g < r_end; g += stride) {
         // a wave covers one 64-ray tile, inside one job
         job_seek<BATCH>(jobs, job1, n_jobs, bcast_first(g - __lane_id()), cur);
+        if (!FRT_CHECK(hdr, cur.j >= 0 && cur.j < n_jobs, kCheckJob) ||
+            !FRT_CHECK(hdr, g >= cur.begin && g < cur.end, kCheckRay)) continue;
         const int j = cur.j;
         const JobDev& J = job_ref<BATCH>(jobs, job1, j);
         int px, py;
         if (!tile_pixel(J, static_cast<long long>(g - cur.begin), px, py)) continue;
         const int p = py * J.width + px;
+        if (!FRT_CHECK(hdr, p >= 0 && p < J.npix, kCheckPixel)) continue;
         const int cls = J.status[p] & 7;
         if (cls < kHit) continue;
         const long long NP = J.npix;

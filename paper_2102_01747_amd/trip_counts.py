@@ -1,15 +1,23 @@
-"""Trip statistics of the march kernels on the bench workload.
+"""Trip statistics and index checks of the instrumented build.
 
-    python -m paper_2102_01747_amd.trip_counts [--build]
+    python -m paper_2102_01747_amd.trip_counts [--build] [--check]
 
-Loads the measurement build libfrt_trips.so (built with --build, or by
-paper_2102_01747_amd._build.build(trip_counters=True)), renders the eight
-1920 x 1080 Mandelbulb views of the bench as one batch, and prints one JSON
-line per march stage: wave-level trips round the outer loop, orbit-loop
-iterations, step paths, refills and claims, and the lanes they served.  With
-a kernel's SQ_INSTS_VALU from rocprofv3 these split its VALU instructions
-between the orbit bodies and the per-trip work.  The counters change only
-what the kernels count, not what they compute.
+Loads the instrumented build libfrt_instr.so (built with --build, or by
+paper_2102_01747_amd._build.build(instrument=True): the same kernels with
+the march kernels' trip counters and the kernels' index checks compiled in),
+renders the eight 1920 x 1080 Mandelbulb views of the bench as one batch,
+and prints one JSON line per march stage: wave-level trips round the outer
+loop, orbit-loop iterations, step paths, refills and claims, and the lanes
+they served.  With a kernel's SQ_INSTS_VALU from rocprofv3 these split its
+VALU instructions between the orbit bodies and the per-trip work.  The
+counters and checks change only what the kernels count, not what they
+compute.
+
+--check also renders with the per-pixel counter planes and requires that the
+lanes the trip counters saw equal the planes' distance estimates and orbit
+bodies; it then runs the degree batch, the 64-job Julia batch and the
+adjoint of the differentiable set, and requires that no index check failed
+in any of them (exit status 1 otherwise).
 """
 import argparse
 import json
@@ -21,28 +29,33 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 NAMES = ("trips", "refills", "body_iterations", "step_paths", "claims", "live_lane_iterations", "step_lanes")
+CHECKS = ("ray index", "pixel index", "job index", "list index")
+
+
+def _checks(word):
+    return [name for k, name in enumerate(CHECKS) if (int(word) >> k) & 1]
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--build", action="store_true", help="build libfrt_trips.so first")
+    ap.add_argument("--build", action="store_true", help="build libfrt_instr.so first")
     ap.add_argument("--check", action="store_true",
-                    help="render with the per-pixel counter planes too and require that the lanes the trip "
-                         "counters saw equal the planes' estimates and orbit bodies (exit status 1 otherwise)")
+                    help="compare the trip counters with the counter planes and run more job sets under the "
+                         "index checks (exit status 1 on any mismatch or failed check)")
     args = ap.parse_args()
     from paper_2102_01747_amd import _build
 
     if args.build:
-        _build.build(trip_counters=True)
+        _build.build(instrument=True)
     import numpy as np
     import torch
 
     import paper_2102_01747_amd as frt
     import workloads as W
 
-    if not os.path.exists(_build.TRIPS_LIB):
-        raise SystemExit("libfrt_trips.so is not built: run with --build")
-    frt.LIB_PATH = _build.TRIPS_LIB
+    if not os.path.exists(_build.INSTR_LIB):
+        raise SystemExit("libfrt_instr.so is not built: run with --build")
+    frt.LIB_PATH = _build.INSTR_LIB
     frt._lib = None
     frt.lib()
     dev = torch.device("cuda:0")
@@ -52,7 +65,7 @@ def main():
     for _ in range(2):
         frt.render_batch(jobs, dev, outs=frames, workspace=ws)
     torch.cuda.synchronize()
-    raw = ws[512:768].cpu().numpy().view(np.uint64)
+    raw = ws[512:776].cpu().numpy().view(np.uint64)
     rays = sum(j["camera"]["width"] * j["camera"]["height"] for j in jobs)
     planes = None
     if args.check:
@@ -75,6 +88,23 @@ def main():
             c["check"] = bool(c["step_lanes"] == est and c["live_lane_iterations"] == bod)
             ok &= c["check"]
         print(json.dumps(c), flush=True)
+    failed = {"bench_views": _checks(raw[32])}
+    if args.check:
+        for name, js in (("degree_batch", W.julia_degree_batch()), ("julia_batch", W.julia_batch())):
+            w2 = frt.alloc_workspace(len(js), dev)
+            frt.render_batch(js, dev, workspace=w2)
+            torch.cuda.synchronize()
+            failed[name] = _checks(w2[768:776].cpu().numpy().view(np.uint64)[0])
+        djobs, targets = W.diff_set()
+        fr = frt.render_batch(djobs, dev)
+        tf = frt.render_batch(targets, dev)
+        gcs = [2.0 * (a["colour"] - b["colour"]) for a, b in zip(fr, tf)]
+        w3 = frt.alloc_workspace(len(djobs), dev)
+        frt.render_backward(djobs, fr, gcs, None, None, dev, workspace=w3)
+        torch.cuda.synchronize()
+        failed["diff_set_backward"] = _checks(w3[768:776].cpu().numpy().view(np.uint64)[0])
+    print(json.dumps({"failed_checks": failed}), flush=True)
+    ok &= all(not v for v in failed.values())
     if not ok:
         raise SystemExit(1)
 

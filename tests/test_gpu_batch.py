@@ -229,26 +229,31 @@ def test_every_ray_claimed_under_any_launch_shape(frt, block, chunk):
     assert torch.equal(single["depth"], ref[3]["depth"])
 
 
-def test_trip_counters_match_the_counter_planes():
-    """The measurement build's trip counters (FRT_TRIP_COUNTERS) against the
-    per-pixel counter planes of the same renders: the lanes that took a
-    step path must equal the distance estimates, and the live lanes of the
-    orbit loop the orbit bodies, exactly, for the primary and the shadow
-    march of the eight 1080p views.  Run in a child process, which loads
-    libfrt_trips.so in place of libfrt.so."""
+def test_instrumented_build_counts_and_checks():
+    """The instrumented build (trip counters and index checks compiled in)
+    against the per-pixel counter planes of the same renders: the lanes that
+    took a step path must equal the distance estimates, and the live lanes
+    of the orbit loop the orbit bodies, exactly, for the primary and the
+    shadow march of the eight 1080p views; and no index check may fail on
+    those views, the degree batch, the 64-job batch or the differentiable
+    set's adjoint.  Run in a child process, which loads libfrt_instr.so in
+    place of libfrt.so."""
     import json
     import os
     import subprocess
     import sys
 
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    if not os.path.exists(os.path.join(root, "paper_2102_01747_amd", "libfrt_trips.so")):
-        pytest.skip("libfrt_trips.so not built")
+    if not os.path.exists(os.path.join(root, "paper_2102_01747_amd", "libfrt_instr.so")):
+        pytest.skip("libfrt_instr.so not built")
     res = subprocess.run([sys.executable, "-m", "paper_2102_01747_amd.trip_counts", "--check"], cwd=root,
                          capture_output=True, text=True, timeout=240)
     print(res.stdout, res.stderr[-2000:])
-    stages = [json.loads(l) for l in res.stdout.splitlines() if l.startswith("{")]
-    assert res.returncode == 0 and len(stages) == 2
+    lines = [json.loads(l) for l in res.stdout.splitlines() if l.startswith("{")]
+    stages = [l for l in lines if "stage" in l]
+    failed = [l for l in lines if "failed_checks" in l]
+    assert res.returncode == 0 and len(stages) == 2 and len(failed) == 1
     for st in stages:
         assert st["check"], st
         assert 0.5 < st["orbit_loop_lane_use"] <= 1.0
+    assert all(not v for v in failed[0]["failed_checks"].values()), failed
