@@ -204,7 +204,11 @@ frt_status frt_render(const frt_camera* cam, const frt_fractal* frac, const frt_
  * the launches captured on the first call with the same (workspace,
  * variants present, launch settings); the job table is re-uploaded before
  * every replay, so
- * parameters and output pointers may change between calls.
+ * parameters and output pointers may change between calls.  Without a
+ * graph, the variants after the first run on the library's side streams of
+ * the current device, forked from `stream` after the queue reset and joined
+ * back into it before the call returns: the work is still ordered on
+ * `stream` as a whole.
  * Errors as frt_render; a job's index appears in frt_last_error().         */
 frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace, size_t ws_bytes,
                             int32_t use_graph, void* stream);

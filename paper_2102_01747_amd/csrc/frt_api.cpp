@@ -476,6 +476,66 @@ frt_status check_workspace(void* workspace, size_t ws_bytes, int32_t n_jobs) {
 
 namespace frt {
 
+namespace {
+// side streams and their fork/join events, per device
+struct SideSet {
+    hipStream_t s[kSideStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSideStreams] = {};
+    bool ready = false;
+};
+std::mutex g_side_mu;
+SideSet g_side[64];
+
+hipError_t side_set(SideSet*& out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    SideSet& ss = g_side[dev];
+    if (!ss.ready) {
+        for (int k = 0; k < kSideStreams; ++k) {
+            e = hipStreamCreateWithFlags(&ss.s[k], hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+            e = hipEventCreateWithFlags(&ss.join[k], hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        ss.ready = true;
+    }
+    out = &ss;
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t fork_streams(hipStream_t main, int n, hipStream_t* side) {
+    if (n < 1 || n > kSideStreams) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    SideSet* ss = nullptr;
+    hipError_t e = side_set(ss);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ss->fork, main);
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+        e = hipStreamWaitEvent(ss->s[k], ss->fork, 0);
+        side[k] = ss->s[k];
+    }
+    return e;
+}
+
+hipError_t join_streams(hipStream_t main, int n) {
+    if (n < 1 || n > kSideStreams) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    SideSet* ss = nullptr;
+    hipError_t e = side_set(ss);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+        e = hipEventRecord(ss->join[k], ss->s[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(main, ss->join[k], 0);
+    }
+    return e;
+}
+
 void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
 
 frt_status record_error(frt_status s, const char* msg) { return fail(s, msg ? msg : ""); }
@@ -721,7 +781,7 @@ frt_status frt_render_batch(const frt_job* jobs, int32_t n_jobs, void* workspace
     };
     if (ng == 0) return scenes();
     if (!use_graph) {
-        hipError_t e = frt::launch_trace(groups.data(), ng, true, dev_jobs, table[0], dhdr, st, timing_marks());
+        hipError_t e = frt::launch_trace(groups.data(), ng, true, dev_jobs, table[0], dhdr, st, timing_marks(), true);
         if (e != hipSuccess) return hip_fail(e, "trace launch");
         return scenes();
     }

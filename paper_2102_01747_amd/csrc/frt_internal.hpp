@@ -32,8 +32,22 @@ struct TraceGroup {
 // marks[0..3] (optional, may be null): events recorded on `stream` before the
 // primary marches, before the normal kernels, before the shadow marches and
 // after the last kernel.
+// fork = true (eager calls only: not under graph capture, not from the
+// entry point that allocates nothing, not with marks): groups after the first
+// run on the library's side streams, forked after the counter reset and
+// joined back into `stream` at the end, so one group's kernels fill the
+// device while another's drain.
 hipError_t launch_trace(const TraceGroup* groups, int n_groups, bool batch, const JobDev* jobs, const JobDev& job1,
-                        WorkspaceHeader* hdr, hipStream_t stream, hipEvent_t* marks = nullptr);
+                        WorkspaceHeader* hdr, hipStream_t stream, hipEvent_t* marks = nullptr, bool fork = false);
+
+// Side streams of the current device (default priority, non-blocking),
+// created on first use.  fork_streams makes the first n wait for everything
+// queued on `main` so far and returns them; join_streams makes `main` wait
+// for everything queued on them.  Both hold a lock across their records and
+// waits.
+constexpr int kSideStreams = 4;
+hipError_t fork_streams(hipStream_t main, int n, hipStream_t* side);
+hipError_t join_streams(hipStream_t main, int n);
 const void* trace_kernel_symbol(int variant, bool batch);
 
 // Batch set-up shared by the batch entry points (frt_api.cpp): validates

@@ -634,9 +634,24 @@ const void* trace_kernel_symbol(int variant, bool batch) {
 }
 
 hipError_t launch_trace(const TraceGroup* groups, int n_groups, bool batch, const JobDev* jobs, const JobDev& job1,
-                        WorkspaceHeader* hdr, hipStream_t stream, hipEvent_t* marks) {
+                        WorkspaceHeader* hdr, hipStream_t stream, hipEvent_t* marks, bool fork) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(2 * kNumVariants * kQueueSlots), 0, stream, hdr);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess && fork && !marks && n_groups > 1 && n_groups <= 1 + kSideStreams) {
+        // group g > 0 on side stream g - 1; each group's stages stay in order
+        hipStream_t side[kSideStreams];
+        e = fork_streams(stream, n_groups - 1, side);
+        for (int g = 0; g < n_groups && e == hipSuccess; ++g) {
+            hipStream_t s = g == 0 ? stream : side[g - 1];
+            for (int stage = 0; stage < 3 && e == hipSuccess; ++stage) {
+                if (stage == 2 && !groups[g].any_shadow) continue;
+                e = batch ? launch_stage_var<true>(groups[g].variant, stage, groups[g].cfg, jobs, job1, hdr, s)
+                          : launch_stage_var<false>(groups[g].variant, stage, groups[g].cfg, jobs, job1, hdr, s);
+            }
+        }
+        const hipError_t ej = join_streams(stream, n_groups - 1);
+        return e != hipSuccess ? e : ej;
+    }
     for (int stage = 0; stage < 3 && e == hipSuccess; ++stage) {
         e = mark(marks, stage, stream);
         for (int g = 0; g < n_groups && e == hipSuccess; ++g) {
