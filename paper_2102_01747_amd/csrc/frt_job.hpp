@@ -150,8 +150,22 @@ enum TripCounter {
     kTripClaims,         // claim attempts on the work queue
     kTripLiveLanes,      // live lanes summed over orbit-loop iterations (orbit bodies)
     kTripStepLanes,      // lanes summed over step paths (distance estimates used)
-    kTripCount
+    kTripCount,          // the counters above are sums over the waves
+    // FRT_WAVE_TIMES: stamps of the 100 MHz real-time counter, each kept as
+    // the latest and (complemented, so one atomic max serves) the earliest:
+    // the waves' starts, their first finding the queue dry and their exits;
+    // and the sum of the exit stamps and the number of waves
+    kTripStartMax = kTripCount,
+    kTripStartMinNot,
+    kTripDrainMax,
+    kTripDrainMinNot,
+    kTripExitMax,
+    kTripExitMinNot,
+    kTripLifeSum,
+    kTripWaves,
+    kTripSlots
 };
+static_assert(kTripSlots <= 16, "each march stage has 16 trip counter slots");
 enum CheckBit {
     kCheckRay = 0,     // a claimed ray index outside its group or its job
     kCheckPixel = 1,   // a pixel index outside its job's planes

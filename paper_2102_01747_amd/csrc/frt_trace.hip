@@ -35,11 +35,33 @@ namespace frt {
 // FRT_TRIP_COUNTERS: a measurement build that counts, per march stage, the
 // wave-level trips, orbit-loop iterations, step paths and claims (summed
 // into the workspace header at each wave's exit); off in the product build.
+// FRT_WAVE_TIMES (implied by FRT_TRIP_COUNTERS): only stamps of the
+// real-time counter at each wave's start, its first finding the queue dry
+// and its exit -- a few instructions per wave outside its loop.
 #ifdef FRT_TRIP_COUNTERS
 #define FRT_TRIP_ADD(k, v) (trip_c[k] += (v))
+#ifndef FRT_WAVE_TIMES
+#define FRT_WAVE_TIMES
+#endif
 #else
 #define FRT_TRIP_ADD(k, v) ((void)0)
 #endif
+#ifdef FRT_WAVE_TIMES
+#define FRT_TRIP_DRAINED() (wave_stamp[1] = __builtin_amdgcn_s_memrealtime())
+#else
+#define FRT_TRIP_DRAINED() ((void)0)
+#endif
+
+// Real-time counter stamps (FRT_WAVE_TIMES): lane 0 folds a stamp into the
+// latest and (complemented) the earliest of slots k and k + 1.  Called only
+// outside the wave's loop (a divergent branch inside it changes how the loop
+// is compiled); the stamps taken inside wait in LDS, not in registers.
+__device__ __forceinline__ void wave_time_mark(unsigned long long* tc, int k, unsigned long long now) {
+    if (__lane_id() == 0) {
+        atomicMax(&tc[k], now);
+        atomicMax(&tc[k + 1], ~now);
+    }
+}
 
 // Bisection stops once the root bracket is narrower than eps(t) / 32 (then one
 // secant step on the final bracket).  A coarser bracket keeps the depth within
@@ -127,6 +149,12 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
 #ifdef FRT_TRIP_COUNTERS
     unsigned long long trip_c[kTripCount] = {};
 #endif
+#ifdef FRT_WAVE_TIMES
+    __shared__ unsigned long long wave_stamps[8][2];   // per wave: start, first dry queue
+    unsigned long long* wave_stamp = wave_stamps[threadIdx.x >> 6];
+    wave_stamp[0] = __builtin_amdgcn_s_memrealtime();
+    wave_stamp[1] = 0ull;
+#endif
     bool drained = false;
     // A wave's first claim is chunk number (its index in the grid), taken
     // without a counter.  The chunks after the grid's first n_waves are
@@ -200,11 +228,6 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
         const unsigned long long m_done = __ballot(phase == kDone);
         const bool exhausted = drained && tmask == 0ull;
         if (m_busy == 0ull && m_done == 0ull && exhausted) {
-#ifdef FRT_TRIP_COUNTERS
-            if (__lane_id() == 0) {
-                for (int k = 0; k < kTripCount; ++k) atomicAdd(&hdr->trips[(SHADOW ? 16 : 0) + k], trip_c[k]);
-            }
-#endif
             break;
         }
         const int waiting = __popcll(m_done) + (exhausted ? 0 : __popcll(__ballot(phase == kIdle)));
@@ -240,6 +263,7 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                     const unsigned long long base = claim();
                     if (base >= r_end) {
                         drained = true;
+                        FRT_TRIP_DRAINED();
                         continue;
                     }
                     q_next = base;
@@ -322,6 +346,7 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                         const unsigned long long base = claim();
                         if (base >= r_end) {
                             drained = true;
+                            FRT_TRIP_DRAINED();
                             break;
                         }
                         q_next = base;
@@ -505,6 +530,25 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
         live |= __ballot(rearm);
         rearm = false;
     }
+#ifdef FRT_TRIP_COUNTERS
+    if (__lane_id() == 0) {
+        for (int k = 0; k < kTripCount; ++k) atomicAdd(&hdr->trips[(SHADOW ? 16 : 0) + k], trip_c[k]);
+    }
+#endif
+#ifdef FRT_WAVE_TIMES
+    {
+        unsigned long long* tc = &hdr->trips[SHADOW ? 16 : 0];
+        const unsigned long long t_exit = __builtin_amdgcn_s_memrealtime();
+        const unsigned long long t_drain = wave_stamp[1];
+        wave_time_mark(tc, kTripStartMax, wave_stamp[0]);
+        wave_time_mark(tc, kTripDrainMax, t_drain ? t_drain : t_exit);
+        wave_time_mark(tc, kTripExitMax, t_exit);
+        if (__lane_id() == 0) {
+            atomicAdd(&tc[kTripLifeSum], t_exit);
+            atomicAdd(&tc[kTripWaves], 1ull);
+        }
+    }
+#endif
 }
 
 // ---------------------------------------------------------------------------

@@ -36,6 +36,23 @@ def _checks(word):
     return [name for k, name in enumerate(CHECKS) if (int(word) >> k) & 1]
 
 
+def wave_times(st):
+    """Wave lifetimes from the real-time counter stamps (100 MHz ticks ->
+    microseconds, from the earliest wave start): the mean, first and last
+    exit, the first and last wave to find the queue dry, and the share of
+    the waves' slots left idle before the last exit."""
+    full = (1 << 64) - 1
+    st = [int(v) for v in st]
+    n = max(st[7], 1)
+    t0 = full - st[1]
+    us = lambda v: round((v - t0) / 100.0, 2)
+    mean_exit = (st[6] / n - t0) / 100.0
+    last = us(st[4])
+    return {"waves": st[7], "start_spread_us": us(st[0]), "queue_dry_us": [us(full - st[3]), us(st[2])],
+            "exit_us": {"first": us(full - st[5]), "mean": round(mean_exit, 2), "last": last},
+            "tail_idle_frac": round(1.0 - mean_exit / last, 4) if last > 0 else 0.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--build", action="store_true", help="build libfrt_instr.so first")
@@ -82,6 +99,7 @@ def main():
         c["orbit_loop_lane_use"] = c["live_lane_iterations"] / (64.0 * c["body_iterations"]) if c["body_iterations"] else 0.0
         c["lanes_per_step_path"] = c["step_lanes"] / c["step_paths"] if c["step_paths"] else 0.0
         c["body_iterations_per_trip"] = c["body_iterations"] / c["trips"] if c["trips"] else 0.0
+        c.update(wave_times(raw[base + len(NAMES):base + len(NAMES) + 8]))
         if planes is not None:
             est, bod = (planes[1], planes[2]) if base == 0 else (planes[6], planes[7])
             c["plane_estimates"], c["plane_bodies"] = int(est), int(bod)
