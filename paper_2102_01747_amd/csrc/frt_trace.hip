@@ -129,9 +129,14 @@ __device__ __forceinline__ void write_shadow(const JobDev& J, int pix, int statu
 // ---------------------------------------------------------------------------
 // The primary march of every variant but n = 8 is held to 64 VGPRs (8 waves
 // per SIMD): left alone the real-power kernel took 66 and ran its 4K sweep
-// about 1.5% slower; the n = 8 kernel fits anyway and was faster without it.
+// about 1.5% slower.  The n = 8 primary march is held to 7 waves per SIMD:
+// left alone it took 106 SGPRs, and with those only 6 of its waves per SIMD
+// were resident (the workgroups of a seventh started as others left, though
+// the occupancy query counts 7); at 94 SGPRs 7 are, and it runs about 2%
+// faster.  The shadow marches are left alone (capped, they spill VGPRs).
 template <int VAR, bool BATCH, bool SHADOW>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(SHADOW || VAR == kVarBulb8 ? 1 : 8)))
+__global__ void __launch_bounds__(512)
+    __attribute__((amdgpu_waves_per_eu(SHADOW ? 1 : (VAR == kVarBulb8 ? 7 : 8))))
 march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                                                     WorkspaceHeader* __restrict__ hdr, int chunk,
                                                     int orbit_lanes, int rare_lanes) {
