@@ -9,7 +9,11 @@ renders the eight 1920 x 1080 Mandelbulb views of the bench as one batch,
 and prints one JSON line per march stage: wave-level trips round the outer
 loop, orbit-loop iterations, step paths, refills and claims, and the lanes
 they served.  With a kernel's SQ_INSTS_VALU from rocprofv3 these split its
-VALU instructions between the orbit bodies and the per-trip work.  The
+VALU instructions between the orbit bodies and the per-trip work.  Each line
+also gives the waves' real-time stamps in microseconds from the first
+wave's start: when the queue was first and last found dry, the first, mean
+and last exit, and the share of the waves' slots left empty before the last
+exit (the end of the launch, where waves finish their last rays).  The
 counters and checks change only what the kernels count, not what they
 compute.
 
