@@ -236,8 +236,8 @@ def test_instrumented_build_counts_and_checks():
     of the orbit loop the orbit bodies, exactly, for the primary and the
     shadow march of the eight 1080p views; and no index check may fail on
     those views, the degree batch, the 64-job batch or the differentiable
-    set's adjoint.  Run in a child process, which loads libfrt_instr.so in
-    place of libfrt.so."""
+    set's adjoint.  The waves' time stamps must be in order.  Run in a child
+    process, which loads libfrt_instr.so in place of libfrt.so."""
     import json
     import os
     import subprocess
@@ -256,4 +256,11 @@ def test_instrumented_build_counts_and_checks():
     for st in stages:
         assert st["check"], st
         assert 0.5 < st["orbit_loop_lane_use"] <= 1.0
+        # the wave stamps: every wave exited, and each found the queue dry
+        # before (or as) it left; the exits lie in order
+        assert st["waves"] >= 1024, st
+        dry, ex = st["queue_dry_us"], st["exit_us"]
+        assert 0.0 <= dry[0] <= dry[1] <= ex["last"], st
+        assert 0.0 < ex["first"] <= ex["mean"] <= ex["last"] < 1e6, st
+        assert 0.0 <= st["tail_idle_frac"] < 1.0, st
     assert all(not v for v in failed[0]["failed_checks"].values()), failed
