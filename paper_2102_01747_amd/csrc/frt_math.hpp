@@ -94,8 +94,10 @@ __device__ __forceinline__ void cpow_c(float& re, float& im) {
     if constexpr (K > 1) {
         const float br = re, bi = im;
         cpow_c<K / 2>(re, im);
+        // the doubling applies to the product, where it can fold into the
+        // multiply as an output modifier; the value is the same
         const float sr = fmaf(re, re, -im * im);
-        const float si = 2.0f * re * im;
+        const float si = (re * im) * 2.0f;
         re = sr;
         im = si;
         if constexpr (K & 1) {
@@ -113,7 +115,7 @@ __device__ __forceinline__ void cpow_int(float& re, float& im, int k) {
     const int top = 31 - __builtin_clz(k);
     for (int bit = top - 1; bit >= 0; --bit) {
         const float sr = fmaf(re, re, -im * im);
-        const float si = 2.0f * re * im;
+        const float si = (re * im) * 2.0f;
         re = sr;
         im = si;
         if ((k >> bit) & 1) {

@@ -105,7 +105,7 @@ __device__ __forceinline__ bool unit_normal(float gx, float gy, float gz, float&
     gx *= sc;
     gy *= sc;
     gz *= sc;
-    const float inv = rsqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
+    const float inv = hw_rsq(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
     nx = gx * inv;
     ny = gy * inv;
     nz = gz * inv;

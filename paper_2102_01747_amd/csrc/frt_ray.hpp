@@ -66,7 +66,7 @@ __device__ __forceinline__ void primary_dir(const JobDev& J, int px, int py, flo
     const float rx = fmaf(u, J.right[0], fmaf(v, J.upv[0], J.fwd[0]));
     const float ry = fmaf(u, J.right[1], fmaf(v, J.upv[1], J.fwd[1]));
     const float rz = fmaf(u, J.right[2], fmaf(v, J.upv[2], J.fwd[2]));
-    const float inv = rsqrtf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+    const float inv = hw_rsq(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
     dx = rx * inv;
     dy = ry * inv;
     dz = rz * inv;
@@ -84,6 +84,16 @@ __device__ __forceinline__ void primary_dir_f64(const JobDev& J, int px, int py,
     dy = ry * inv;
     dz = rz * inv;
 }
+
+// Work-item and dispatch geometry along x (every grid here is 1-D and made of
+// whole blocks), read from the hardware registers and the dispatch packet.
+// HIP's threadIdx / blockIdx / blockDim / gridDim go through device-library
+// functions, which are not inlined into kernels built with another
+// floating-point mode than the library's and then become real calls.
+__device__ __forceinline__ unsigned thread_x() { return __builtin_amdgcn_workitem_id_x(); }
+__device__ __forceinline__ unsigned block_x() { return __builtin_amdgcn_workgroup_id_x(); }
+__device__ __forceinline__ unsigned block_threads() { return __builtin_amdgcn_workgroup_size_x(); }
+__device__ __forceinline__ unsigned grid_threads() { return __builtin_amdgcn_grid_size_x(); }
 
 __device__ __forceinline__ unsigned long long bcast_first(unsigned long long v) {
     const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));

@@ -156,7 +156,7 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
 #endif
 #ifdef FRT_WAVE_TIMES
     __shared__ unsigned long long wave_stamps[8][2];   // per wave: start, first dry queue
-    unsigned long long* wave_stamp = wave_stamps[threadIdx.x >> 6];
+    unsigned long long* wave_stamp = wave_stamps[thread_x() >> 6];
     wave_stamp[0] = __builtin_amdgcn_s_memrealtime();
     wave_stamp[1] = 0ull;
 #endif
@@ -167,11 +167,11 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
     // kQueueSlots is the j-th of slot s); a wave claims from its block's
     // slot, and from the others once that share is spent.  All waves
     // claiming through one address would queue on it.
-    const unsigned wpb = blockDim.x >> 6;
-    const unsigned long long n_waves = static_cast<unsigned long long>(gridDim.x) * wpb;
+    const unsigned wpb = block_threads() >> 6;
+    const unsigned long long n_waves = grid_threads() >> 6;
     const unsigned long long first_chunk =
-        static_cast<unsigned long long>(blockIdx.x) * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const unsigned home = blockIdx.x % kQueueSlots;
+        static_cast<unsigned long long>(block_x()) * wpb + __builtin_amdgcn_readfirstlane(thread_x() >> 6);
+    const unsigned home = block_x() % kQueueSlots;
     unsigned spent = 0u;   // slots whose share is spent (wave-uniform)
     bool first_claim = true;
     auto claim = [&]() -> unsigned long long {   // the chunk's first ray, or r_end
@@ -208,7 +208,7 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
     // shadow-casting pixels not yet handed to a lane (wave-uniform)
     unsigned long long tile_g = 0, tmask = 0;
     __shared__ uint8_t slots[8][64];   // per wave: lane index of the k-th set bit of tmask
-    uint8_t* slot = slots[threadIdx.x >> 6];
+    uint8_t* slot = slots[thread_x() >> 6];
 
     int phase = kIdle;
     int jb = 0, pix = 0, entry = -1, status = 0, steps = 0, rk = 0, hit_it = 0;
@@ -574,9 +574,9 @@ __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ 
         r_begin = hdr->range[VAR][0];
         r_end = hdr->range[VAR][1];
     }
-    const unsigned long long stride = static_cast<unsigned long long>(gridDim.x) * blockDim.x;
+    const unsigned long long stride = grid_threads();
     JobCursor cur;
-    for (unsigned long long g = r_begin + static_cast<unsigned long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (unsigned long long g = r_begin + static_cast<unsigned long long>(block_x()) * block_threads() + thread_x();
          g < r_end; g += stride) {
         // a wave covers one 64-ray tile, inside one job
         job_seek<BATCH>(jobs, job1, n_jobs, bcast_first(g - __lane_id()), cur);
@@ -629,7 +629,7 @@ __global__ void __launch_bounds__(256) normal_kernel(const JobDev* __restrict__ 
 }
 
 __global__ void reset_queue_kernel(WorkspaceHeader* hdr) {
-    if (threadIdx.x < 2 * kNumVariants * kQueueSlots) hdr->queue[threadIdx.x][0] = 0ull;
+    if (thread_x() < 2 * kNumVariants * kQueueSlots) hdr->queue[thread_x()][0] = 0ull;
 }
 
 static hipError_t mark(hipEvent_t* marks, int k, hipStream_t stream) {

@@ -8,6 +8,11 @@ rays.  The test compiles frt_trace.hip to gfx950 assembly with the library's
 own flags and fails if any select or conditional scalar move reads a condition
 flag last written by an add, subtract or shift with a vector compare in
 between -- the shape of that miscompile.
+
+The same assembly must hold no function calls: the forward kernels are built
+in another floating-point mode than the device library's, and a library
+function reached from them (HIP's thread-index accessors, rsqrtf) is then not
+inlined but called, with the call's register convention around it.
 """
 import os
 import re
@@ -58,16 +63,30 @@ def test_detector_flags_the_pattern():
     assert stale_flag_selects(good) == []
 
 
-@pytest.mark.timeout(600)
-def test_march_kernels_have_no_stale_flag_select(tmp_path):
+@pytest.fixture(scope="module")
+def trace_asm(tmp_path_factory):
+    """gfx950 assembly of frt_trace.hip, compiled with the library's flags."""
     hipcc = _build.hipcc()
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
     src = os.path.join(_build.CSRC, "frt_trace.hip")
-    out = tmp_path / "trace.s"
+    out = tmp_path_factory.mktemp("asm") / "trace.s"
     cmd = [hipcc, "--offload-arch=" + _build.ARCH, "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", "-I", _build.INCLUDE, "-I", _build.CSRC, "--cuda-device-only", "-S", src, "-o", str(out)]
+           "-packed-fp32-ops"] + _build.SOURCE_FLAGS.get("frt_trace.hip", []) + [
+           "-I", _build.INCLUDE, "-I", _build.CSRC, "--cuda-device-only", "-S", src, "-o", str(out)]
     res = subprocess.run(cmd, capture_output=True, text=True)
     assert res.returncode == 0, res.stderr[-2000:]
-    bad = stale_flag_selects(out.read_text())
+    return out.read_text()
+
+
+@pytest.mark.timeout(600)
+def test_march_kernels_have_no_stale_flag_select(trace_asm):
+    bad = stale_flag_selects(trace_asm)
     assert not bad, "selects on a stale condition flag: %s" % bad[:5]
+
+
+@pytest.mark.timeout(600)
+def test_forward_kernels_make_no_calls(trace_asm):
+    calls = re.findall(r"^\s*s_swappc_b64.*$", trace_asm, flags=re.M)
+    callees = sorted(set(re.findall(r"(\w+)@rel32@lo", trace_asm)))
+    assert not calls, "calls in the forward kernels (%d), to %s" % (len(calls), callees)
