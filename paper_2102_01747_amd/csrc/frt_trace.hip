@@ -466,71 +466,66 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
         }
 #endif
         if (!__builtin_amdgcn_inverse_ballot_w64(live) && (phase == kCut || phase == kMarch || phase == kRefine)) {
-            {
-                const DEResult de = orb.result(P);
-                evals += 1u;
-                bodies += static_cast<unsigned>(de.bodies);
-                const float d = de.d;
-                if (phase == kCut) {
-                    // cut face: the entry point is inside when its orbit does
-                    // not escape or the estimate is below eps
-                    if (de.it == P.max_iter || d < fmaf(er, t, ea)) {
-                        status = SHADOW ? kFlagShadowed : kHitCut;
-                        if (!SHADOW) hit_it = de.it;
-                        phase = kDone;
-                    } else {
-                        phase = kMarch;
-                    }
-                }
-                if (phase == kMarch || phase == kRefine) {
-                    // g = d - eps(t).  One bracket update serves the march
-                    // (Listing 3) and the bisection: a sample above the
-                    // eps-region becomes the bracket's left end lt (g(lt) =
-                    // lh >= 0), one below it the right end t1 (g(t1) = gb <
-                    // 0).  A march lane keeps t1 = the interval's end until
-                    // its first sample below, which ends the march.
-                    const bool ref = !SHADOW && phase == kRefine;
-                    const float g = d - fmaf(er, t, ea);
-                    const bool below = g < 0.0f;
-                    if (!ref) {
-                        ++steps;
-                        if (!SHADOW) hit_it = de.it;
-                    }
-                    if constexpr (!SHADOW) {
-                        if (below) { t1 = t; gb = g; } else { lt = t; lh = g; }
-                    }
-                    if (!ref && !below) {
-                        t += fminf(d, clamp);
-                        if (t > t1) {
-                            status = SHADOW ? 0 : kMissTmax;
-                            phase = kDone;
-                        } else if (steps >= max_steps) {
-                            status = SHADOW ? kFlagShadowed : (kHitExhausted | kFlagUnrefined);
-                            phase = kDone;
-                        }
-                    } else if (SHADOW || (!ref && steps == 1)) {
-                        // shadow rays stop at their first hit; a primary ray
-                        // whose first sample is inside has no bracket
-                        status = SHADOW ? kFlagShadowed : (kHit | kFlagUnrefined);
-                        phase = kDone;
-                    } else {
-                        // the bracket [lt, t1] holds a root of g: bisect it
-                        // down to eps / 32, then one secant step
-                        if (ref) ++rk; else { status = kHit; rk = 0; }
-                        if (rk < refine_iters && t1 - lt > kRefineTol * fmaf(er, t1, ea)) {
-                            phase = kRefine;
-                            t = 0.5f * (lt + t1);
-                        } else {
-                            t = fmaf(-gb, __fdividef(t1 - lt, gb - lh), t1);
-                            phase = kDone;
-                        }
-                    }
-                }
-                if (phase == kCut || phase == kMarch || phase == kRefine) {
-                    orb.init(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz));
-                    rearm = true;
-                }
+            // One pass with no branches: nearly every wave has lanes in
+            // each case, so every case's values are computed and each lane
+            // selects its own.
+            const DEResult de = orb.result(P);
+            evals += 1u;
+            bodies += static_cast<unsigned>(de.bodies);
+            const float d = de.d;
+            const float eps_t = fmaf(er, t, ea);
+            // g = d - eps(t).  One bracket update serves the march (Listing
+            // 3) and the bisection: a sample above the eps-region becomes the
+            // bracket's left end lt (g(lt) = lh >= 0), one below it the right
+            // end t1 (g(t1) = gb < 0).  A march lane keeps t1 = the
+            // interval's end until its first sample below, which ends the
+            // march.
+            const float g = d - eps_t;
+            const bool below = g < 0.0f;
+            // cut face: the entry point is inside when its orbit does not
+            // escape or the estimate is below eps; otherwise the lane
+            // marches on from this sample
+            const bool cut_in = phase == kCut && (de.it == P.max_iter || d < eps_t);
+            const bool ref = !SHADOW && phase == kRefine;
+            const bool mar = phase != kRefine && !cut_in;
+            steps += mar ? 1 : 0;
+            if constexpr (!SHADOW) {
+                hit_it = ref ? hit_it : de.it;
+                t1 = below ? t : t1;
+                gb = below ? g : gb;
+                lt = below ? lt : t;
+                lh = below ? lh : g;
             }
+            const bool adv = mar && !below;
+            const float tn = t + fminf(d, clamp);
+            const bool miss = adv && tn > t1;
+            const bool exhausted = adv && !miss && steps >= max_steps;
+            // shadow rays stop at their first hit; a primary ray whose first
+            // sample is inside has no bracket
+            const bool first = mar && below && (SHADOW || steps == 1);
+            // the bracket [lt, t1] holds a root of g: bisect it down to
+            // eps / 32, then one secant step
+            const bool bis = !SHADOW && (ref || (mar && below)) && !first;
+            rk = ref ? rk + 1 : 0;
+            const float w = t1 - lt;
+            const bool cont = bis && rk < refine_iters && w > kRefineTol * fmaf(er, t1, ea);
+            const float tmid = 0.5f * (lt + t1);
+            const float tsec = fmaf(-gb, __fdividef(w, gb - lh), t1);
+            t = adv ? tn : (cont ? tmid : (bis ? tsec : t));
+            if constexpr (SHADOW) {
+                status = (cut_in || exhausted || first) ? kFlagShadowed : (miss ? 0 : status);
+            } else {
+                status = cut_in ? kHitCut
+                       : miss ? kMissTmax
+                       : exhausted ? (kHitExhausted | kFlagUnrefined)
+                       : first ? (kHit | kFlagUnrefined)
+                       : (bis && !ref) ? kHit : status;
+            }
+            const bool done = cut_in || miss || exhausted || first || (bis && !cont);
+            phase = done ? kDone : (cont ? kRefine : kMarch);
+            // the next sample's orbit (finished lanes restart one too, unused)
+            orb.init(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz));
+            rearm = !done;
         }
         live |= __ballot(rearm);
         rearm = false;
