@@ -510,7 +510,9 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
             const float w = t1 - lt;
             const bool cont = bis && rk < refine_iters && w > kRefineTol * fmaf(er, t1, ea);
             const float tmid = 0.5f * (lt + t1);
-            const float tsec = fmaf(-gb, __fdividef(w, gb - lh), t1);
+            // (the hardware reciprocal: the secant only has to land inside a
+            // bracket already narrower than eps / 32)
+            const float tsec = fmaf(-gb, w * hw_rcp(gb - lh), t1);
             t = adv ? tn : (cont ? tmid : (bis ? tsec : t));
             if constexpr (SHADOW) {
                 status = (cut_in || exhausted || first) ? kFlagShadowed : (miss ? 0 : status);
