@@ -22,6 +22,13 @@
 // one atomic claims `chunk` ray indices, handed out by ballot + mbcnt.  A wave
 // leaves its loop when the ballot of busy lanes is empty and the queue is
 // drained.  One launch of each kernel serves all renders of a batch.
+//
+// The build compiles this file alone with FP32 denormals flushed, the
+// hardware's IEEE mode off and no NaN or signed-zero semantics, so that a
+// doubling or power-of-two scale folds into the output modifier of the
+// instruction producing the value.  No value here that an output depends on
+// is a denormal, a NaN or a signed zero; work-item IDs come from the amdgcn
+// builtins (device-library code would not inline into this mode).
 #include <hip/hip_runtime.h>
 
 #include "frt_fractal.hpp"
