@@ -63,9 +63,12 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 def kernel_sources_sha256(names=KERNEL_SOURCES):
     """SHA-256 of kernel code: the sources with comments and whitespace
     removed, so that an edit of a comment keeps the profiled figures (the
-    sources hold no string literal with a comment marker)."""
+    sources hold no string literal with a comment marker), and the extra
+    compile flags the build gives any of them."""
     import hashlib
     import re
+
+    from paper_2102_01747_amd import _build
 
     h = hashlib.sha256()
     for name in names:
@@ -73,6 +76,8 @@ def kernel_sources_sha256(names=KERNEL_SOURCES):
             code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
         code = re.sub(r"//[^\n]*", " ", code)
         h.update(" ".join(code.split()).encode())
+        if _build.SOURCE_FLAGS.get(name):
+            h.update((" flags: " + " ".join(_build.SOURCE_FLAGS[name])).encode())
     return h.hexdigest()
 
 

@@ -1,6 +1,7 @@
 """The guard that keeps a profiled traffic figure in the bench line only
 while the forward kernels are the ones profiled: the hash of the kernel
-code ignores comments and layout but not code."""
+code ignores comments and layout but not code, nor the build flags of
+its sources."""
 import os
 import shutil
 
@@ -37,3 +38,13 @@ def test_comments_and_layout_do_not_change_the_hash(tmp_path):
 def test_code_changes_the_hash(tmp_path):
     base = _hash_with(tmp_path, None, None)
     assert _hash_with(tmp_path, "frt_trace.hip", lambda s: s.replace("kMaxBodiesPerTrip = 64", "kMaxBodiesPerTrip = 32")) != base
+
+
+def test_build_flags_change_the_hash(monkeypatch):
+    from paper_2102_01747_amd import _build
+
+    base = bench.kernel_sources_sha256()
+    flags = dict(_build.SOURCE_FLAGS)
+    flags["frt_trace.hip"] = [f for f in flags.get("frt_trace.hip", []) if f != "-fno-signed-zeros"]
+    monkeypatch.setattr(_build, "SOURCE_FLAGS", flags)
+    assert bench.kernel_sources_sha256() != base
