@@ -142,11 +142,35 @@ def host_cpu_model():
     return platform.processor() or "unknown"
 
 
+def timed_median(fn, reps, windows=5):
+    """Per-call milliseconds of fn: one untimed call, then `windows` windows of
+    `reps` back-to-back calls between HIP events on the current stream, and
+    the median window (a host stall inside one short window would otherwise
+    set the figure)."""
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(windows):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        e.synchronize()
+        per.append(s.elapsed_time(e) / reps)
+    return sorted(per)[len(per) // 2]
+
+
+TIMING = "median of 5 windows of back-to-back calls (HIP events on the current stream)"
+
+
 def adjoint_leg(frt, dev, reps):
     """Differentiable set: 8 Julia + 8 Mandelbulb renders of 512x512 with a
     cut plane, loss = squared colour error to target renders at offset
     parameters.  Times the forward batch and the adjoint launch (HIP events
-    on the current stream), and the finite-difference gradient the adjoint
+    on the current stream, the median of 5 windows), and the finite-difference gradient the adjoint
     replaces: central differences need 2 P renders per job (P parameters:
     c and plane for Julia, n and plane for the Mandelbulb), issued as 2 max(P)
     batch renders with one parameter of every job offset."""
@@ -165,15 +189,7 @@ def adjoint_leg(frt, dev, reps):
     grads = None
 
     def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.record()
-        for _ in range(reps):
-            fn()
-        e.record()
-        e.synchronize()
-        return s.elapsed_time(e) / reps
+        return timed_median(fn, reps)
 
     def backward():
         nonlocal grads
@@ -222,7 +238,7 @@ def adjoint_leg(frt, dev, reps):
             "grads_per_s": n / ((t_f + t_b) * 1e-3), "forward_ms": t_f, "backward_ms": t_b,
             "backward_over_forward": t_b / t_f, "fd_renders_per_gradient": "2 x (8 Julia / 5 Mandelbulb parameters)",
             "fd_grads_per_s": n / (t_fd * 1e-3), "speedup_vs_fd": (t_fd) / (t_f + t_b),
-            "rel_err_target": 1e-3}
+            "rel_err_target": 1e-3, "timing": TIMING}
 
 
 def batch_leg(frt, dev, reps):
@@ -230,9 +246,8 @@ def batch_leg(frt, dev, reps):
     workload (seeded c, cut plane, resolution, iterations and eps) launched
     one by one (frt_render, one stream, one workspace), as one batch
     (frt_render_batch) and as a replayed HIP graph of that batch; times from
-    events on the current stream, speedups over one by one."""
-    import torch
-
+    events on the current stream (the median of 5 windows), speedups over
+    one by one."""
     import workloads as W
 
     jobs = W.julia_batch()
@@ -241,15 +256,7 @@ def batch_leg(frt, dev, reps):
     ws1 = frt.alloc_workspace(1, dev)
 
     def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.record()
-        for _ in range(reps):
-            fn()
-        e.record()
-        e.synchronize()
-        return s.elapsed_time(e) / reps
+        return timed_median(fn, reps)
 
     t_one = timed(lambda: [frt.render(j, dev, out=f, workspace=ws1) for j, f in zip(jobs, frames)])
     t_batch = timed(lambda: frt.render_batch(jobs, dev, outs=frames, workspace=ws))
@@ -259,7 +266,7 @@ def batch_leg(frt, dev, reps):
     return {"workload": "julia_batch_64_uneven", "renders": len(jobs), "rays": rays,
             "one_by_one_ms": t_one, "batched_ms": t_batch, "graph_ms": t_graph,
             "speedup": t_one / t_batch, "speedup_graph": t_one / t_graph,
-            "batched_mrays_per_s": rays / (t_batch * 1e-3) / 1e6, "target_speedup": 2.0}
+            "batched_mrays_per_s": rays / (t_batch * 1e-3) / 1e6, "target_speedup": 2.0, "timing": TIMING}
 
 
 def hardware_fp32(flop, launch_ms):
