@@ -22,8 +22,8 @@ SPACE = {
     "block": [64, 128, 256, 512],
     "chunk": [64, 128, 256, 512, 1024],
     "waves_per_simd": [2, 4, 6, 8, 0],
-    "orbit_lanes": [1, 4, 8, 16, 24, 32, 48],
-    "rare_lanes": [2, 4, 8, 16, 32, 48],
+    "orbit_lanes": [1, 4, 8, 12, 16, 24, 32, 48],
+    "rare_lanes": [2, 4, 8, 16, 24, 32, 48],
 }
 KEYS = ["block", "chunk", "waves_per_simd", "orbit_lanes", "rare_lanes"]
 
