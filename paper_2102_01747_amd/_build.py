@@ -50,6 +50,11 @@ SANITIZE_HOST = "-O1 -g -Xarch_host -fsanitize=address -Xarch_host -fsanitize=un
 # loads like libfrt.so through FRT_LIB_PATH.
 INSTR_LIB = os.path.join(PKG, "libfrt_instr.so")
 
+# The strict build: the same sources with no per-source flags, every kernel
+# in strict IEEE semantics; the tests require the forward kernels' outputs to
+# equal the product build's bit for bit.
+STRICT_LIB = os.path.join(PKG, "libfrt_strict.so")
+
 
 def _run(cmd, verbose):
     if verbose:
@@ -63,11 +68,11 @@ def _run(cmd, verbose):
 
 
 def build(verbose: bool = False, sanitize: bool = False, out: str = None, instrument: bool = False,
-          csrc: str = None, source_flags: dict = None) -> str:
+          csrc: str = None, source_flags: dict = None, strict: bool = False) -> str:
     csrc = csrc or CSRC
-    source_flags = SOURCE_FLAGS if source_flags is None else source_flags
+    source_flags = ({} if strict else SOURCE_FLAGS) if source_flags is None else source_flags
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(csrc, s))]
-    dest = out or (INSTR_LIB if instrument else LIB)
+    dest = out or (INSTR_LIB if instrument else STRICT_LIB if strict else LIB)
     tmp = dest + ".tmp"
     opt = SANITIZE_HOST.split() if sanitize else ["-O3"]
     if instrument:
