@@ -140,7 +140,8 @@ __device__ __forceinline__ void write_shadow(const JobDev& J, int pix, int statu
 // left alone it took 106 SGPRs, and with those only 6 of its waves per SIMD
 // were resident (the workgroups of a seventh started as others left, though
 // the occupancy query counts 7); at 94 SGPRs 7 are, and it runs about 2%
-// faster.  The shadow marches are left alone (capped, they spill VGPRs).
+// faster.  The shadow marches are left alone: held to 8 waves per SIMD the
+// n = 8 one (56 VGPRs) spilled SGPRs and ran about 4% slower.
 template <int VAR, bool BATCH, bool SHADOW>
 __global__ void __launch_bounds__(512)
     __attribute__((amdgpu_waves_per_eu(SHADOW ? 1 : (VAR == kVarBulb8 ? 7 : 8))))
@@ -216,6 +217,9 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
     unsigned long long tile_g = 0, tmask = 0;
     __shared__ uint8_t slots[8][64];   // per wave: lane index of the k-th set bit of tmask
     uint8_t* slot = slots[thread_x() >> 6];
+    // per wave: the shadow rays gathered for a refill (ray index within their job)
+    __shared__ int gathered_rays[SHADOW ? 8 : 1][64];
+    int* gathered = gathered_rays[SHADOW ? (thread_x() >> 6) : 0];
 
     int phase = kIdle;
     int jb = 0, pix = 0, entry = -1, status = 0, steps = 0, rk = 0, hit_it = 0;
@@ -350,48 +354,74 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
             // Shadow rays: claim 64-ray tiles and read the tile's status bytes
             // once (one load per lane); the normal kernel flagged the pixels
             // that cast a shadow ray, so the tile's rays reduce to a 64-bit
-            // mask and the idle lanes take its set bits in order, through
-            // this wave's slot table in LDS.
+            // mask.  The flagged rays of as many tiles of one job as the idle
+            // lanes can take are gathered into this wave's table in LDS (ray
+            // index within the job), then handed out to the idle lanes in
+            // order in one pass, so the per-ray set-up runs once per refill
+            // rather than once per tile.
             while (idle != 0ull && (tmask != 0ull || !drained)) {
-                if (tmask == 0ull) {
-                    if (q_next >= q_end) {
-                        const unsigned long long base = claim();
-                        if (base >= r_end) {
+                const unsigned need = static_cast<unsigned>(__popcll(idle));
+                const unsigned lane = __lane_id();
+                unsigned got = 0;   // rays gathered (wave-uniform)
+                int gj = cur.j;     // their job (wave-uniform)
+                while (got < need && (tmask != 0ull || !drained)) {
+                    if (tmask == 0ull) {
+                        if (q_next >= q_end) {
+                            const unsigned long long base = claim();
+                            if (base >= r_end) {
+                                drained = true;
+                                FRT_TRIP_DRAINED();
+                                break;
+                            }
+                            q_next = base;
+                            q_end = min(base + static_cast<unsigned long long>(chunk), r_end);
+                        }
+                        tile_g = q_next;
+                        q_next += 64ull;
+                        job_seek<BATCH>(jobs, job1, n_jobs, tile_g, cur);
+                        if (!FRT_CHECK(hdr, cur.j >= 0 && cur.j < n_jobs, kCheckJob) ||
+                            !FRT_CHECK(hdr, tile_g >= cur.begin && tile_g + 64ull <= cur.end && tile_g < r_end,
+                                       kCheckRay)) {
                             drained = true;
-                            FRT_TRIP_DRAINED();
+                            tmask = 0ull;
                             break;
                         }
-                        q_next = base;
-                        q_end = min(base + static_cast<unsigned long long>(chunk), r_end);
+                        const JobDev& J = job_ref<BATCH>(jobs, job1, cur.j);
+                        int px, py;
+                        bool cast = false;
+                        if (tile_pixel(J, static_cast<long long>(tile_g - cur.begin) + lane, px, py))
+                            cast = (J.status[py * J.width + px] & kFlagShadowRay) != 0;
+                        tmask = __ballot(cast);
+                        // a tile of another job waits for the next refill
+                        if (got > 0 && cur.j != gj) break;
+                        gj = cur.j;
+                        continue;
                     }
-                    tile_g = q_next;
-                    q_next += 64ull;
-                    job_seek<BATCH>(jobs, job1, n_jobs, tile_g, cur);
-                    if (!FRT_CHECK(hdr, cur.j >= 0 && cur.j < n_jobs, kCheckJob) ||
-                        !FRT_CHECK(hdr, tile_g >= cur.begin && tile_g + 64ull <= cur.end && tile_g < r_end, kCheckRay)) {
-                        drained = true;
-                        break;
+                    // the tile's set bits in order: the first `take` join the
+                    // table, the rest stay in tmask
+                    const unsigned nbits = static_cast<unsigned>(__popcll(tmask));
+                    const unsigned take = min(nbits, need - got);
+                    if ((tmask >> lane) & 1ull) {
+                        const unsigned k = lane_rank(tmask);
+                        slot[k] = static_cast<uint8_t>(lane);
+                        if (k < take) gathered[got + k] = static_cast<int>(tile_g - cur.begin) + static_cast<int>(lane);
                     }
-                    const JobDev& J = job_ref<BATCH>(jobs, job1, cur.j);
-                    int px, py;
-                    bool cast = false;
-                    if (tile_pixel(J, static_cast<long long>(tile_g - cur.begin) + __lane_id(), px, py))
-                        cast = (J.status[py * J.width + px] & kFlagShadowRay) != 0;
-                    tmask = __ballot(cast);
-                    continue;
+                    __builtin_amdgcn_wave_barrier();
+                    if (take < nbits) {
+                        const unsigned cut = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(slot[take]));
+                        tmask &= ~((1ull << cut) - 1ull);
+                    } else {
+                        tmask = 0ull;
+                    }
+                    got += take;
+                    __builtin_amdgcn_wave_barrier();
                 }
-                const unsigned lane = __lane_id();
-                if ((tmask >> lane) & 1ull) slot[lane_rank(tmask)] = static_cast<uint8_t>(lane);
-                __builtin_amdgcn_wave_barrier();
-                const unsigned nbits = static_cast<unsigned>(__popcll(tmask));
-                const unsigned nidle = static_cast<unsigned>(__popcll(idle));
+                if (got == 0) break;
                 const unsigned rank = lane_rank(idle);
-                if (phase == kIdle && rank < nbits) {
-                    // the tile's job is the cursor's
-                    const int j = cur.j;
-                    const JobDev& J = job_ref<BATCH>(jobs, job1, j);
+                if (phase == kIdle && rank < got) {
+                    const JobDev& J = job_ref<BATCH>(jobs, job1, gj);
                     int px, py;
-                    tile_pixel(J, static_cast<long long>(tile_g - cur.begin) + slot[rank], px, py);
+                    tile_pixel(J, static_cast<long long>(gathered[rank]), px, py);
                     const int p = py * J.width + px;
                     const long long NP = J.npix;
                     const float nx = J.normal[p], ny = J.normal[NP + p], nz = J.normal[2 * NP + p];
@@ -411,7 +441,7 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                     status = 0;
                     float lo, hi;
                     if (ray_interval(J, ox, oy, oz, dx, dy, dz, eps, lo, hi, entry)) {
-                        jb = j;
+                        jb = gj;
                         pix = p;
                         if constexpr (BATCH) P = orbit_params(J);
                         clamp = J.clamp;
@@ -427,13 +457,6 @@ march_kernel(const JobDev* __restrict__ jobs, const JobDev job1,
                         orb.init(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz));
                         rearm = true;
                     }
-                }
-                // keep the bits not handed out: from the nidle-th set bit on
-                if (nidle >= nbits) {
-                    tmask = 0ull;
-                } else {
-                    const unsigned cut = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(slot[nidle]));
-                    tmask &= ~((1ull << cut) - 1ull);
                 }
                 __builtin_amdgcn_wave_barrier();
                 idle = __ballot(phase == kIdle);
